@@ -1,0 +1,188 @@
+"""Seeded synthetic inputs shared by the tests, the bench and the oracle's timing.
+
+This module only draws numbers.  It holds none of the sort's arithmetic, so the
+CPU oracle and the HIP path can both be fed from it without sharing any code
+of the method itself.
+
+Every stream is counter based: ``u64(seed, i)`` is output ``i`` of a SplitMix64
+generator (Steele, Lea and Flood, "Fast splittable pseudorandom number
+generators", OOPSLA 2014) whose state starts at ``seed``:
+
+    z  = seed + (i + 1) * 0x9E3779B97F4A7C15          (mod 2**64)
+    z  = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9
+    z  = (z ^ (z >> 27)) * 0x94D049BB133111EB
+    out = z ^ (z >> 31)
+
+so any element can be recomputed on its own, on the host or on the device.
+
+The workloads stand in for the paper's inputs (Section V: uniform, normal,
+right-skewed and exponential data sets, one billion entries, and a Twitter
+graph), which are not available here; the shapes below are synthetic.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+M1 = np.uint64(0xBF58476D1CE4E5B9)
+M2 = np.uint64(0x94D049BB133111EB)
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    z = z.astype(np.uint64, copy=True)
+    with np.errstate(over="ignore"):
+        z ^= z >> np.uint64(30)
+        z *= M1
+        z ^= z >> np.uint64(27)
+        z *= M2
+        z ^= z >> np.uint64(31)
+    return z
+
+
+def u64(seed: int, idx) -> np.ndarray:
+    """SplitMix64 output number ``idx`` (array or scalar) of the stream ``seed``."""
+    i = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + (i + np.uint64(1)) * GAMMA
+    return _mix(z)
+
+
+def u64_range(seed: int, start: int, count: int) -> np.ndarray:
+    return u64(seed, np.arange(start, start + count, dtype=np.uint64))
+
+
+def unit_double(bits: np.ndarray) -> np.ndarray:
+    """Top 53 bits of a u64 as a double in [0, 1)."""
+    return (bits >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+# --------------------------------------------------------------------------
+# Plain inputs
+# --------------------------------------------------------------------------
+
+def uniform_keys(n: int, seed: int, dtype=np.uint64, start: int = 0) -> np.ndarray:
+    k = u64_range(seed, start, n)
+    if dtype == np.uint32:
+        return (k >> np.uint64(32)).astype(np.uint32)
+    return k
+
+
+def index_values(n: int, start: int = 0) -> np.ndarray:
+    """Payload equal to the input index (so stability can be read off the output)."""
+    return np.arange(start, start + n, dtype=np.uint32)
+
+
+def zipf_cdf(n_ranks: int, s: float) -> np.ndarray:
+    w = 1.0 / np.power(np.arange(1, n_ranks + 1, dtype=np.float64), s)
+    c = np.cumsum(w)
+    return c / c[-1]
+
+
+def zipf_ranks(bits: np.ndarray, cdf: np.ndarray) -> np.ndarray:
+    """Inverse-CDF draw of ranks 1..len(cdf) from 53-bit uniforms."""
+    u = unit_double(bits)
+    r = np.searchsorted(cdf, u, side="right") + 1
+    return np.minimum(r, len(cdf)).astype(np.uint64)
+
+
+def duplicate_heavy_keys(n: int, seed: int = 3, zipf_s: float = 1.1,
+                         n_values: int = 1000, start: int = 0) -> np.ndarray:
+    """Half the keys equal one value V, the rest Zipf(s) over ``n_values`` values.
+
+    The top bit of ``u64(seed, i)`` picks V = u64(seed*11, 0); otherwise the
+    remaining bits draw a Zipf rank r and the key is u64(seed*11 + 1, r).  V is
+    checked to differ from every Zipf value.
+    """
+    u = u64_range(seed, start, n)
+    heavy = np.uint64(u64(seed * 11, 0))
+    cdf = zipf_cdf(n_values, zipf_s)
+    ranks = zipf_ranks(u << np.uint64(1), cdf)
+    table = u64(seed * 11 + 1, np.arange(0, n_values + 1, dtype=np.uint64))
+    assert not np.any(table[1:] == heavy)
+    keys = table[ranks]
+    top = (u >> np.uint64(63)) == np.uint64(1)
+    keys[top] = heavy
+    return keys
+
+
+def normal_u32(n: int, seed: int, start: int = 0) -> np.ndarray:
+    """clamp(round(2^31 + 2^29 z)) with z ~ N(0,1) by Box-Muller on two streams."""
+    a = unit_double(u64_range(seed, start, n))
+    b = unit_double(u64_range(seed + 0x5bd1e995, start, n))
+    z = np.sqrt(-2.0 * np.log1p(-a)) * np.cos(2.0 * math.pi * b)
+    v = np.rint(2.0 ** 31 + 2.0 ** 29 * z)
+    return np.clip(v, 0, 2 ** 32 - 1).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------
+# Batched instances
+# --------------------------------------------------------------------------
+
+BATCH_DISTS = ("uniform", "normal", "sorted", "reverse")
+
+
+def batch_sizes(B: int, seed: int, lo: int = 1024, hi: int = 4194304) -> np.ndarray:
+    """n_b = floor(exp(U(ln lo, ln hi))), log-uniform instance sizes."""
+    u = unit_double(u64_range(seed, 0, B))
+    n = np.floor(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo))))
+    return np.clip(n, lo, hi).astype(np.int64)
+
+
+def batch_dist_ids(B: int, seed: int) -> np.ndarray:
+    return (u64_range(seed + 1, 0, B) % np.uint64(4)).astype(np.int64)
+
+
+def batch_instance_keys_u32(b: int, n: int, dist: int, seed: int) -> np.ndarray:
+    s = (seed * 1000003 + b * 7919 + 17) & 0xFFFFFFFFFFFFFFFF
+    if dist == 0:
+        return uniform_keys(n, s, np.uint32)
+    if dist == 1:
+        return normal_u32(n, s)
+    k = np.sort(uniform_keys(n, s, np.uint32))
+    return k if dist == 2 else k[::-1].copy()
+
+
+def batch_u32(B: int, seed: int = 4, lo: int = 1024, hi: int = 4194304):
+    """Keys (u32), values (local index, u32) and seg_offsets[B+1] of a batch."""
+    sizes = batch_sizes(B, seed, lo, hi)
+    dists = batch_dist_ids(B, seed)
+    offs = np.zeros(B + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes).astype(np.uint64)
+    keys = np.empty(int(offs[-1]), dtype=np.uint32)
+    vals = np.empty(int(offs[-1]), dtype=np.uint32)
+    for b in range(B):
+        a, e = int(offs[b]), int(offs[b + 1])
+        keys[a:e] = batch_instance_keys_u32(b, e - a, int(dists[b]), seed)
+        vals[a:e] = np.arange(e - a, dtype=np.uint32)
+    return keys, vals, offs
+
+
+# --------------------------------------------------------------------------
+# Serving request stream
+# --------------------------------------------------------------------------
+
+SERVE_DISTS = ("uniform", "zipf", "sorted", "reverse")
+
+
+def serve_requests(n_req: int, seed: int = 5, rate_per_s: float = 2000.0,
+                   lo: int = 10000, hi: int = 67108864):
+    """Poisson arrivals (exponential gaps), log-uniform sizes, distribution ids."""
+    gaps = -np.log1p(-unit_double(u64_range(seed, 0, n_req))) / rate_per_s
+    arrivals = np.cumsum(gaps)
+    sizes = batch_sizes(n_req, seed + 2, lo, hi)
+    dists = (u64_range(seed + 3, 0, n_req) % np.uint64(4)).astype(np.int64)
+    return arrivals, sizes, dists
+
+
+def serve_pool_u64(dist: int, n: int, seed: int = 5) -> np.ndarray:
+    s = seed * 101 + dist
+    if dist == 0:
+        return uniform_keys(n, s)
+    if dist == 1:
+        cdf = zipf_cdf(1000000, 1.2)
+        r = zipf_ranks(u64_range(s, 0, n), cdf)
+        return u64(s + 7, r)
+    k = np.sort(uniform_keys(n, s))
+    return k if dist == 2 else k[::-1].copy()
