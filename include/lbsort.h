@@ -1,0 +1,178 @@
+/*
+ * lbsort — load-balanced sample sort on one AMD MI355X (gfx950).
+ *
+ * C ABI of the library.  The operation is the distributed sort of Khatami et
+ * al., "A Load-Balanced Parallel and Distributed Sorting Algorithm Implemented
+ * with PGX.D" (arXiv 1611.00463), Section IV, run on one GPU: the P processors
+ * of the paper become P virtual processors, each owning one contiguous block
+ * of the input, and the six steps are
+ *
+ *   1. each block is sorted locally (stable LSD radix sort, Section IV.A);
+ *   2. regular samples are taken from each sorted block (Section IV.B);
+ *   3. P-1 splitters are chosen from the pooled samples (step 3);
+ *   4. every splitter is searched in every sorted block, and the investigator
+ *      divides runs of keys equal to a duplicated splitter (Section IV.B,
+ *      Fig. 3);
+ *   5. the ranges are exchanged: block i's slice for partition k lands at the
+ *      receive offset known from the broadcast range table (Section IV.C);
+ *   6. each partition merges what it received with the handler (Section IV.A,
+ *      Fig. 2), yielding the globally sorted data; smaller keys sit in
+ *      partitions with smaller ids (Section IV.C).
+ *
+ * Keys are unsigned 32- or 64-bit integers in ascending unsigned order.
+ * Values are opaque 32-bit payloads carried with their keys.  In the default
+ * investigator mode (COUNT) the output equals a stable sort of the input.
+ *
+ * Conventions shared by every entry point
+ *   - All data pointers are DEVICE pointers unless marked "host".
+ *   - The caller owns every buffer.  The library allocates no device memory
+ *     in the sort calls; scratch space comes from the caller's workspace.
+ *   - Two-phase workspace: call once with ws == NULL to receive the needed
+ *     size in *ws_bytes (host), allocate it, and call again.  A workspace
+ *     smaller than needed returns LBSORT_ERR_WORKSPACE_TOO_SMALL.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL for
+ *     the default stream) and is asynchronous: results are valid once the
+ *     stream has been synchronised.  Inputs are read-only and must not
+ *     overlap outputs or the workspace.  Calls that share a workspace must
+ *     not run concurrently.
+ *   - Every function returns a status code (0 = success, negative = error)
+ *     and never aborts; lbsort_last_error() returns this thread's last error
+ *     text.  Errors found on the device (a bounded wait that gave up, a
+ *     malformed segment table) are latched in the workspace and returned by
+ *     lbsort_check().
+ */
+#ifndef LBSORT_H
+#define LBSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LBSORT_OK 0
+#define LBSORT_ERR_INVALID_ARG (-1)
+#define LBSORT_ERR_WORKSPACE_TOO_SMALL (-2)
+#define LBSORT_ERR_UNSUPPORTED (-3)
+#define LBSORT_ERR_HIP (-4)
+#define LBSORT_ERR_OOM (-5)
+#define LBSORT_ERR_DEVICE (-6)
+
+/* key and value types */
+#define LBSORT_U32 1
+#define LBSORT_U64 2
+#define LBSORT_NOVAL 0
+#define LBSORT_VAL_U32 1
+
+/* investigator modes (step 4, Section IV.B) */
+#define LBSORT_INV_COUNT 0 /* default: equal-key runs split at global ranks floor(kN/P) */
+#define LBSORT_INV_NONE 1  /* plain regular sampling, no investigator (Fig. 3b)       */
+#define LBSORT_INV_PAPER 2 /* each block's equal-key range cut into d+1 equal pieces  */
+
+/* limits */
+#define LBSORT_MAX_P 1024
+#define LBSORT_MAX_SAMPLES (1u << 20)
+
+typedef struct lbsort_params {
+  uint32_t P;            /* virtual processors = output partitions, 1..LBSORT_MAX_P      */
+  uint32_t s;            /* regular samples per block; 0 = the paper's budget: one 256 KB
+                            read buffer over all processors, max(1, 262144 / (P * key bytes)) */
+  uint32_t investigator; /* LBSORT_INV_*                                                     */
+  uint32_t fanin;        /* handler merge fan-in F per pass: 0 = tuned, else 2, 4, 8 or 16   */
+  uint32_t merge_tile;   /* elements per merge tile: 0 = tuned, else 1024, 2048 or 4096     */
+  uint32_t reserved;     /* must be 0                                                        */
+} lbsort_params;
+
+/* Partition outputs (device arrays).  For a batch every array is stacked per
+ * instance: instance b's part_offsets are at part_offsets[b*(P+1)], etc. */
+typedef struct lbsort_parts {
+  uint64_t *part_offsets; /* [P+1] required: G_0 = 0 <= G_1 <= ... <= G_P = n; partition k
+                             is output positions [G_k, G_{k+1}) (relative to the segment) */
+  uint64_t *part_counts;  /* [P]   optional (NULL): G_{k+1} - G_k                            */
+  void *splitters;        /* [P-1] optional: v_1..v_{P-1}, key type                          */
+  uint64_t *send_counts;  /* [P*P] optional: C[i][k] = keys block i sends to partition k     */
+  uint64_t *cuts;         /* [P*(P+1)] optional: c[i][k], block i sends sorted positions
+                             [c[i][k], c[i][k+1]) to partition k                             */
+} lbsort_parts;
+
+/*
+ * Sort n keys (steps 1-6).  keys_in/keys_out: n keys of `key_type`.
+ * Block i of the input is positions [floor(i n / P), floor((i+1) n / P)).
+ * n may be 0.  params may be NULL (P = 1, all defaults).
+ */
+int lbsort_sort_keys(int key_type, const void *keys_in, void *keys_out, uint64_t n,
+                     const lbsort_params *params, const lbsort_parts *parts, void *ws,
+                     size_t *ws_bytes, void *stream);
+
+/* Same, carrying one 32-bit value per key (val_type = LBSORT_VAL_U32). */
+int lbsort_sort_pairs(int key_type, int val_type, const void *keys_in, const void *vals_in,
+                      void *keys_out, void *vals_out, uint64_t n, const lbsort_params *params,
+                      const lbsort_parts *parts, void *ws, size_t *ws_bytes, void *stream);
+
+/*
+ * Sort B independent instances at once ("sort multiple different data
+ * simultaneously", Section IV.C).  Instance b is input positions
+ * [seg_offsets[b], seg_offsets[b+1]) of keys_in/vals_in and is sorted into the
+ * same positions of keys_out/vals_out.  seg_offsets is a DEVICE array of B+1
+ * non-decreasing values with seg_offsets[0] = 0 and seg_offsets[B] = total_n.
+ * Every instance uses the same params; parts arrays are stacked per instance
+ * and offsets are relative to the instance's segment.  vals_in may be NULL
+ * with val_type = LBSORT_NOVAL.  Nothing is read back to the host, so the
+ * whole call can be captured into a HIP graph.
+ */
+int lbsort_sort_batch(int key_type, int val_type, const void *keys_in, const void *vals_in,
+                      void *keys_out, void *vals_out, const uint64_t *seg_offsets, uint32_t B,
+                      uint64_t total_n, const lbsort_params *params, const lbsort_parts *parts,
+                      void *ws, size_t *ws_bytes, void *stream);
+
+/*
+ * Step 1 alone: every block of every instance sorted on its own (stable),
+ * written to the same positions of keys_out/vals_out.  Same arguments as
+ * lbsort_sort_batch without the partition outputs.
+ */
+int lbsort_local_sort(int key_type, int val_type, const void *keys_in, const void *vals_in,
+                      void *keys_out, void *vals_out, const uint64_t *seg_offsets, uint32_t B,
+                      uint64_t total_n, const lbsort_params *params, void *ws, size_t *ws_bytes,
+                      void *stream);
+
+/*
+ * Synchronise `stream` and return the device error latched in `ws` by the
+ * last call that used it (LBSORT_OK if none), then clear it.
+ */
+int lbsort_check(void *ws, void *stream);
+
+/* Static text for a status code, and this thread's last error message. */
+const char *lbsort_status_string(int status);
+const char *lbsort_last_error(void);
+
+/*
+ * Measure the candidate (fan-in, merge tile) settings for one shape on the
+ * current device and record the fastest in the tuning cache (host JSON file
+ * at `cache_path`, or $LBSORT_TUNE_CACHE, or no file if both are NULL/empty).
+ * Allocates its own scratch device memory.  n is the instance size; B > 1
+ * tunes the batched form with B instances of n keys.  On success the chosen
+ * fan-in and tile are stored to *fanin / *merge_tile (host, may be NULL).
+ */
+int lbsort_autotune(int key_type, int val_type, uint64_t n, uint32_t B, uint32_t P,
+                    const char *cache_path, uint32_t *fanin, uint32_t *merge_tile);
+
+/* Load a tuning cache written by lbsort_autotune (host path). */
+int lbsort_load_tuning(const char *cache_path);
+
+/*
+ * Measurement aid.  While enabled (on != 0), every kernel launch of the sort
+ * calls is bracketed by two HIP events recorded on the call's stream.
+ * lbsort_profile_read synchronises those events, writes one line per kernel
+ * name, "name launches total_ms\n", into buf (host, len bytes, NUL
+ * terminated), clears the records and returns the number of bytes needed
+ * (excluding the NUL).  Not thread safe; meant for benchmarks.
+ */
+int lbsort_profile_enable(int on);
+int lbsort_profile_read(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBSORT_H */

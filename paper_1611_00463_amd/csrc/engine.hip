@@ -1,0 +1,353 @@
+// Host side of lbsort: argument checks, the workspace layout, and the launch
+// sequence of one call (steps 1-6 of Section IV), all enqueued on the
+// caller's stream with no host synchronisation in between.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/lbsort.h"
+#include "lbsort_internal.hpp"
+#include "tuning.hpp"
+
+namespace lbs {
+
+void launch_plan(const Plan& p, hipStream_t s);
+void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s);
+template <typename K>
+void launch_hist(const Plan& p, const K* src, hipStream_t s);
+template <typename K, bool HASV>
+void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s);
+template <typename K, bool HASV>
+void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s);
+template <typename K>
+void launch_split(const Plan& p, const K* sorted, u64 max_samples, const void* out_offsets, void* out_counts,
+                  void* out_send, void* out_cuts, void* out_split, hipStream_t s);
+template <typename K, bool HASV>
+void launch_merge_level(const Plan& p, u32 level, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s);
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+__global__ void k_seg2(u64* seg, u64 n) {
+  if (threadIdx.x == 0) {
+    seg[0] = 0;
+    seg[1] = n;
+  }
+}
+
+static inline u64 align256(u64 x) { return (x + 255) & ~(u64)255; }
+
+struct Shape {
+  int key_type, val_type;
+  u32 B, P, s, inv, F, TM, L, D;
+  u64 total_n;
+  bool single;      // one instance whose size the host knows
+  bool has_small, has_large;
+  u64 max_tiles, max_samples;
+  u32 ng0;          // merge groups of pass 0 (the largest pass)
+  u64 mslots;
+  bool local_only;  // step 1 only
+};
+
+struct Layout {
+  u64 counters, blk_start, tstart, small_list, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
+      splitters, mtile, mcut, tmpk, tmpv, seg, total;
+};
+
+static Layout make_layout(const Shape& sh) {
+  Layout l;
+  const u64 K = sh.key_type == LBSORT_U64 ? 8 : 4;
+  const u64 NB = (u64)sh.B * sh.P, P = sh.P, B = sh.B;
+  u64 o = 0;
+  auto take = [&](u64 bytes) {
+    u64 at = o;
+    o = align256(o + (bytes ? bytes : 1));
+    return at;
+  };
+  l.counters = take(C_COUNT * 4);
+  l.blk_start = take((NB + 1) * 8);
+  l.tstart = take((NB + 1) * 4);
+  l.small_list = take(NB * 4);
+  l.samp_start = take((NB + 1) * 8);
+  l.hist = take(NB * sh.D * RADIX * 4);
+  l.status = take(sh.max_tiles * RADIX * 8);
+  l.samples = take(sh.max_samples * K);
+  l.pool = take(sh.max_samples * K);
+  l.lo = take(B * P * (P - 1) * 8);
+  l.hi = take(B * P * (P - 1) * 8);
+  l.cuts = take(B * P * (P + 1) * 8);
+  l.Dm = take(B * (P + 1) * P * 8);
+  l.G = take(B * (P + 1) * 8);
+  l.splitters = take(B * (P - 1) * K);
+  l.mtile = take(((u64)sh.ng0 + 1) * 4);
+  l.mcut = take(sh.mslots * sh.F * 8);
+  const u64 stages = (u64)sh.D + sh.L;
+  const bool need_tmp = stages > 1;
+  l.tmpk = take(need_tmp ? sh.total_n * K : 0);
+  l.tmpv = take(need_tmp && sh.val_type ? sh.total_n * 4 : 0);
+  l.seg = take(16);
+  l.total = o;
+  return l;
+}
+
+static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbsort_params* prm, bool local_only,
+                      Shape& sh) {
+  if (key_type != LBSORT_U32 && key_type != LBSORT_U64)
+    return fail(LBSORT_ERR_INVALID_ARG, "key_type must be LBSORT_U32 or LBSORT_U64 (got %d)", key_type);
+  if (val_type != LBSORT_NOVAL && val_type != LBSORT_VAL_U32)
+    return fail(LBSORT_ERR_INVALID_ARG, "val_type must be LBSORT_NOVAL or LBSORT_VAL_U32 (got %d)", val_type);
+  lbsort_params d = {1, 0, LBSORT_INV_COUNT, 0, 0, 0};
+  const lbsort_params& p = prm ? *prm : d;
+  if (p.P < 1 || p.P > LBSORT_MAX_P) return fail(LBSORT_ERR_INVALID_ARG, "P must be in [1, %d] (got %u)", LBSORT_MAX_P, p.P);
+  if (p.investigator > 2) return fail(LBSORT_ERR_INVALID_ARG, "unknown investigator mode %u", p.investigator);
+  if (p.s > LBSORT_MAX_SAMPLES) return fail(LBSORT_ERR_INVALID_ARG, "s must be <= %u (got %u)", LBSORT_MAX_SAMPLES, p.s);
+  if (p.fanin != 0 && p.fanin != 2 && p.fanin != 4 && p.fanin != 8 && p.fanin != 16)
+    return fail(LBSORT_ERR_INVALID_ARG, "fanin must be 0, 2, 4, 8 or 16 (got %u)", p.fanin);
+  if (p.merge_tile != 0 && p.merge_tile != 1024 && p.merge_tile != 2048 && p.merge_tile != 4096)
+    return fail(LBSORT_ERR_INVALID_ARG, "merge_tile must be 0, 1024, 2048 or 4096 (got %u)", p.merge_tile);
+  if (p.reserved != 0) return fail(LBSORT_ERR_INVALID_ARG, "reserved must be 0");
+  if (B < 1) return fail(LBSORT_ERR_INVALID_ARG, "B must be >= 1");
+  if (total_n >= (1ull << 44)) return fail(LBSORT_ERR_UNSUPPORTED, "total_n must be < 2^44");
+  if ((u64)B * p.P > (1ull << 26)) return fail(LBSORT_ERR_UNSUPPORTED, "B * P must be <= 2^26");
+  sh.key_type = key_type;
+  sh.val_type = val_type;
+  sh.B = B;
+  sh.P = p.P;
+  sh.total_n = total_n;
+  sh.inv = p.investigator;
+  sh.local_only = local_only;
+  const u32 kb = key_type == LBSORT_U64 ? 8 : 4;
+  sh.D = kb * 8 / RADIX_BITS;
+  sh.s = p.s ? p.s : (262144u / (p.P * kb) > 0 ? 262144u / (p.P * kb) : 1u);
+  // merge fan-in and tile: explicit, else tuned, else defaults
+  Tuned tu = tuning_lookup(key_type, val_type, total_n / B, B, p.P);
+  u32 F = p.fanin ? p.fanin : tu.fanin;
+  if (!F) {
+    F = 2;
+    while (F < p.P && F < 16) F *= 2;
+    if (p.P > 16) F = 8;
+  }
+  sh.F = F;
+  sh.TM = p.merge_tile ? p.merge_tile : (tu.merge_tile ? tu.merge_tile : 2048u);
+  u32 L = 0;
+  for (u64 span = 1; span < p.P; span *= F) ++L;
+  sh.L = local_only ? 0 : L;
+  const u64 NB = (u64)B * p.P;
+  sh.single = (B == 1);
+  if (sh.single) {
+    sh.has_small = sh.has_large = false;
+    sh.max_tiles = 0;
+    sh.max_samples = 0;
+    for (u32 i = 0; i < p.P; ++i) {
+      const u64 n = (u64)(((unsigned __int128)(i + 1) * total_n) / p.P) - (u64)(((unsigned __int128)i * total_n) / p.P);
+      if (n >= (1ull << 32)) return fail(LBSORT_ERR_UNSUPPORTED, "a block of 2^32 keys or more (raise P)");
+      if (n > (u64)SORT_TILE) {
+        sh.has_large = true;
+        sh.max_tiles += (n + SORT_TILE - 1) / SORT_TILE;
+      } else if (n > 0) {
+        sh.has_small = true;
+      }
+      sh.max_samples += n < sh.s ? n : sh.s;
+    }
+  } else {
+    sh.has_small = sh.has_large = true;
+    sh.max_tiles = total_n / SORT_TILE + NB;
+    const u64 cap = NB * sh.s;
+    sh.max_samples = total_n < cap ? total_n : cap;
+  }
+  if (sh.max_tiles >= (1ull << 31)) return fail(LBSORT_ERR_UNSUPPORTED, "too many radix tiles");
+  const u64 Q0 = (p.P + F - 1) / F;
+  sh.ng0 = (u32)(NB * Q0);
+  sh.mslots = sh.L ? total_n / sh.TM + 2ull * sh.ng0 + 1 : 0;
+  return LBSORT_OK;
+}
+
+template <typename K, bool HASV>
+static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin, K* kout, u32* vout,
+               const u64* seg_in, const lbsort_parts* parts, char* ws, hipStream_t st) {
+  Plan p;
+  memset(&p, 0, sizeof p);
+  p.B = sh.B;
+  p.P = sh.P;
+  p.NB = sh.B * sh.P;
+  p.s = sh.s;
+  p.D = sh.D;
+  p.inv = sh.inv;
+  p.F = sh.F;
+  p.L = sh.L;
+  p.TM = sh.TM;
+  p.max_tiles = (u32)sh.max_tiles;
+  p.total_n = sh.total_n;
+  p.blk_start = (u64*)(ws + lay.blk_start);
+  p.tstart = (u32*)(ws + lay.tstart);
+  p.small_list = (u32*)(ws + lay.small_list);
+  p.counters = (u32*)(ws + lay.counters);
+  p.hist = (u32*)(ws + lay.hist);
+  p.status = (u64*)(ws + lay.status);
+  p.samp_start = (u64*)(ws + lay.samp_start);
+  p.samples = ws + lay.samples;
+  p.pool = ws + lay.pool;
+  p.lo = (u64*)(ws + lay.lo);
+  p.hi = (u64*)(ws + lay.hi);
+  p.cuts = (u64*)(ws + lay.cuts);
+  p.Dm = (u64*)(ws + lay.Dm);
+  p.G = (u64*)(ws + lay.G);
+  p.splitters = ws + lay.splitters;
+  p.mtile = (u32*)(ws + lay.mtile);
+  p.mcut = (u64*)(ws + lay.mcut);
+  p.ng_max = sh.ng0;
+  p.mslots_max = (u32)sh.mslots;
+  if (seg_in) {
+    p.seg = seg_in;
+  } else {
+    u64* seg = (u64*)(ws + lay.seg);
+    hipLaunchKernelGGL(k_seg2, dim3(1), dim3(64), 0, st, seg, sh.total_n);
+    p.seg = seg;
+  }
+  K* tk = (K*)(ws + lay.tmpk);
+  u32* tv = (u32*)(ws + lay.tmpv);
+  const u32 S = sh.D + sh.L;
+  auto dk = [&](u32 j) -> K* { return ((S - 1 - j) % 2 == 0) ? kout : tk; };
+  auto dv = [&](u32 j) -> u32* { return ((S - 1 - j) % 2 == 0) ? vout : tv; };
+
+  launch_fill32(p.counters, C_COUNT, 0, st);
+  if (sh.has_large) {
+    launch_fill32(p.hist, (u64)p.NB * sh.D * RADIX, 0, st);
+    launch_fill32((u32*)p.status, sh.max_tiles * RADIX * 2, 0, st);
+  }
+  launch_plan(p, st);
+  if (sh.has_large) launch_hist<K>(p, kin, st);
+  if (sh.has_small) launch_small_sort<K, HASV>(p, kin, vin, dk(sh.D - 1), dv(sh.D - 1), st);
+  if (sh.has_large)
+    for (u32 j = 0; j < sh.D; ++j)
+      launch_onesweep<K, HASV>(p, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);
+  if (!sh.local_only) {
+    const K* sorted = dk(sh.D - 1);
+    launch_split<K>(p, sorted, sh.max_samples, parts->part_offsets, parts->part_counts, parts->send_counts,
+                    parts->cuts, parts->splitters, st);
+    for (u32 l = 0; l < sh.L; ++l)
+      launch_merge_level<K, HASV>(p, l, dk(sh.D - 1 + l), dv(sh.D - 1 + l), dk(sh.D + l), dv(sh.D + l), st);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return LBSORT_OK;
+}
+
+static int dispatch(const Shape& sh, const void* kin, const void* vin, void* kout, void* vout, const u64* seg,
+                    const lbsort_parts* parts, void* ws, size_t* ws_bytes, void* stream) {
+  const Layout lay = make_layout(sh);
+  if (!ws_bytes) return fail(LBSORT_ERR_INVALID_ARG, "ws_bytes must not be NULL");
+  if (!ws) {
+    *ws_bytes = lay.total;
+    return LBSORT_OK;
+  }
+  if (*ws_bytes < lay.total)
+    return fail(LBSORT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, need %llu", *ws_bytes,
+                (unsigned long long)lay.total);
+  if (((uintptr_t)ws & 255) != 0) return fail(LBSORT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (sh.total_n > 0 && (!kin || !kout)) return fail(LBSORT_ERR_INVALID_ARG, "keys_in/keys_out must not be NULL");
+  if (sh.val_type && sh.total_n > 0 && (!vin || !vout))
+    return fail(LBSORT_ERR_INVALID_ARG, "vals_in/vals_out must not be NULL with LBSORT_VAL_U32");
+  if (!sh.local_only && (!parts || !parts->part_offsets))
+    return fail(LBSORT_ERR_INVALID_ARG, "parts->part_offsets is required");
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const bool v = sh.val_type == LBSORT_VAL_U32;
+  if (sh.key_type == LBSORT_U64) {
+    if (v) return run<u64, true>(sh, lay, (const u64*)kin, (const u32*)vin, (u64*)kout, (u32*)vout, seg, parts, w, st);
+    return run<u64, false>(sh, lay, (const u64*)kin, nullptr, (u64*)kout, nullptr, seg, parts, w, st);
+  }
+  if (v) return run<u32, true>(sh, lay, (const u32*)kin, (const u32*)vin, (u32*)kout, (u32*)vout, seg, parts, w, st);
+  return run<u32, false>(sh, lay, (const u32*)kin, nullptr, (u32*)kout, nullptr, seg, parts, w, st);
+}
+
+}  // namespace lbs
+
+using namespace lbs;
+
+extern "C" {
+
+int lbsort_sort_keys(int key_type, const void* keys_in, void* keys_out, uint64_t n, const lbsort_params* params,
+                     const lbsort_parts* parts, void* ws, size_t* ws_bytes, void* stream) {
+  Shape sh;
+  int rc = make_shape(key_type, LBSORT_NOVAL, 1, n, params, false, sh);
+  if (rc) return rc;
+  return dispatch(sh, keys_in, nullptr, keys_out, nullptr, nullptr, parts, ws, ws_bytes, stream);
+}
+
+int lbsort_sort_pairs(int key_type, int val_type, const void* keys_in, const void* vals_in, void* keys_out,
+                      void* vals_out, uint64_t n, const lbsort_params* params, const lbsort_parts* parts, void* ws,
+                      size_t* ws_bytes, void* stream) {
+  Shape sh;
+  int rc = make_shape(key_type, val_type, 1, n, params, false, sh);
+  if (rc) return rc;
+  return dispatch(sh, keys_in, vals_in, keys_out, vals_out, nullptr, parts, ws, ws_bytes, stream);
+}
+
+int lbsort_sort_batch(int key_type, int val_type, const void* keys_in, const void* vals_in, void* keys_out,
+                      void* vals_out, const uint64_t* seg_offsets, uint32_t B, uint64_t total_n,
+                      const lbsort_params* params, const lbsort_parts* parts, void* ws, size_t* ws_bytes,
+                      void* stream) {
+  Shape sh;
+  int rc = make_shape(key_type, val_type, B, total_n, params, false, sh);
+  if (rc) return rc;
+  if (!seg_offsets) return fail(LBSORT_ERR_INVALID_ARG, "seg_offsets must not be NULL");
+  return dispatch(sh, keys_in, vals_in, keys_out, vals_out, seg_offsets, parts, ws, ws_bytes, stream);
+}
+
+int lbsort_local_sort(int key_type, int val_type, const void* keys_in, const void* vals_in, void* keys_out,
+                      void* vals_out, const uint64_t* seg_offsets, uint32_t B, uint64_t total_n,
+                      const lbsort_params* params, void* ws, size_t* ws_bytes, void* stream) {
+  Shape sh;
+  int rc = make_shape(key_type, val_type, B, total_n, params, true, sh);
+  if (rc) return rc;
+  if (!seg_offsets) return fail(LBSORT_ERR_INVALID_ARG, "seg_offsets must not be NULL");
+  return dispatch(sh, keys_in, vals_in, keys_out, vals_out, seg_offsets, nullptr, ws, ws_bytes, stream);
+}
+
+int lbsort_check(void* ws, void* stream) {
+  if (!ws) return fail(LBSORT_ERR_INVALID_ARG, "ws must not be NULL");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "stream synchronize failed: %s", hipGetErrorString(e));
+  u32 err = 0;
+  e = hipMemcpy(&err, (char*)ws + 0 + C_ERR * 4, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "reading the device error word failed: %s", hipGetErrorString(e));
+  if (err) {
+    const u32 zero = 0;
+    hipMemcpy((char*)ws + C_ERR * 4, &zero, 4, hipMemcpyHostToDevice);
+    return fail(LBSORT_ERR_DEVICE, "device error bits 0x%x (%s%s%s%s)", err, (err & E_SPIN) ? "look-back wait gave up " : "",
+                (err & E_SEG) ? "malformed seg_offsets " : "", (err & E_SELECT) ? "merge selection did not converge " : "",
+                (err & E_RANGE) ? "block of 2^32 keys or more" : "");
+  }
+  return LBSORT_OK;
+}
+
+const char* lbsort_status_string(int status) {
+  switch (status) {
+    case LBSORT_OK: return "ok";
+    case LBSORT_ERR_INVALID_ARG: return "invalid argument";
+    case LBSORT_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case LBSORT_ERR_UNSUPPORTED: return "unsupported";
+    case LBSORT_ERR_HIP: return "HIP runtime error";
+    case LBSORT_ERR_OOM: return "out of device memory";
+    case LBSORT_ERR_DEVICE: return "error detected on the device";
+    default: return "unknown status";
+  }
+}
+
+const char* lbsort_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

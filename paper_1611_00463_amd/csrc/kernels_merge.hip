@@ -1,0 +1,365 @@
+// Steps 5 and 6 of Section IV on the GPU: the exchange and the handler merge.
+//
+// Partition k receives one sorted run from every block (block i's cut slice
+// [c[i][k], c[i][k+1]) of its sorted data).  The handler of Fig. 2 merges runs
+// pairwise in rounds (1->0, 3->2, ...; then 2->0, 6->4; ...), ties going to the
+// lower run, which keeps the sort stable.  Here one pass over the data merges
+// F runs at once (F = 2 is the paper's tree level by level; F = 4, 8, 16 do
+// log2(F) of its rounds per pass inside LDS), so P runs take ceil(log_F P)
+// passes.  The exchange is not a separate copy: the first merge pass reads
+// the cut slices straight from the sorted blocks, and every pass writes to the
+// receive offsets of the range table (D[i][k] = G_k + sum_{i'<i} C[i'][k]).
+//
+// Each pass cuts its output into tiles of TM elements.  The split of a tile
+// boundary among the F runs is found by a wave-wide multi-pivot selection
+// (k_partition); a workgroup then loads the tile's F slices into LDS and runs
+// the pairwise merge tree there (k_merge).
+#include "lbsort_internal.hpp"
+
+namespace lbs {
+
+struct Level {
+  u32 level;  // 0-based pass
+  u32 RS;     // blocks per input run  = F^level
+  u32 GS;     // blocks per output run = F^(level+1)
+  u32 Q;      // groups (output runs) per partition = ceil(P / GS)
+  u32 NG;     // groups in all = B * P * Q
+};
+
+__device__ inline void group_info(const Plan& p, const Level& L, u32 gidx, u64& out_off, u64& out_len) {
+  const u32 g = gidx % L.Q, bk = gidx / L.Q, k = bk % p.P, b = bk / p.P;
+  const u32 i0 = g * L.GS, i1 = min(i0 + L.GS, p.P);
+  const u64* Db = p.Dm + (u64)b * (p.P + 1) * p.P;
+  out_off = p.seg[b] + Db[(u64)i0 * p.P + k];
+  out_len = Db[(u64)i1 * p.P + k] - Db[(u64)i0 * p.P + k];
+}
+
+// Input run r of group gidx: element offset in the pass's source buffer and length.
+__device__ inline void run_info(const Plan& p, const Level& L, u32 gidx, u32 r, u64& off, u64& len) {
+  const u32 g = gidx % L.Q, bk = gidx / L.Q, k = bk % p.P, b = bk / p.P;
+  const u32 i0 = g * L.GS + r * L.RS;
+  if (i0 >= p.P) {
+    off = 0;
+    len = 0;
+    return;
+  }
+  if (L.level == 0) {
+    const u64* c = p.cuts + ((u64)b * p.P + i0) * (p.P + 1);
+    off = p.blk_start[b * p.P + i0] + c[k];
+    len = c[k + 1] - c[k];
+  } else {
+    const u32 i1 = min(i0 + L.RS, p.P);
+    const u64* Db = p.Dm + (u64)b * (p.P + 1) * p.P;
+    off = p.seg[b] + Db[(u64)i0 * p.P + k];
+    len = Db[(u64)i1 * p.P + k] - Db[(u64)i0 * p.P + k];
+  }
+  // keep the run inside its instance whatever the metadata says
+  const u64 lim = p.seg[b + 1];
+  if (off > lim) off = lim;
+  if (len > lim - off) len = lim - off;
+}
+
+// Tile counts of every group of this pass, prefix-summed (single workgroup).
+__global__ __launch_bounds__(1024) void k_merge_plan(Plan p, Level L) {
+  __shared__ u64 s_w[16];
+  const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  u64 carry = 0;
+  for (u32 base = 0; base < L.NG; base += 1024) {
+    const u32 g = base + tid;
+    u64 nt = 0;
+    if (g < L.NG) {
+      u64 off, len;
+      group_info(p, L, g, off, len);
+      nt = (len + p.TM - 1) / p.TM;
+    }
+    u64 x = nt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      u64 y = __shfl_up(x, o);
+      if (lane >= (u32)o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    if (w == 0) {
+      u64 t = lane < 16 ? s_w[lane] : 0;
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        u64 y = __shfl_up(t, o);
+        if (lane >= (u32)o) t += y;
+      }
+      if (lane < 16) s_w[lane] = t;
+    }
+    __syncthreads();
+    const u64 ex = carry + (w ? s_w[w - 1] : 0) + x - nt;
+    if (g < L.NG) p.mtile[g] = (u32)ex;
+    carry += s_w[15];
+    __syncthreads();
+  }
+  if (tid == 0) p.mtile[L.NG] = (u32)carry;
+}
+
+// ----------------------------------------------------------------- selection
+// Split of the first `a` elements of the stable merge of F sorted runs (order:
+// key, then run, then position).  Lane l works on run l % F.  Each round every
+// run with a non-empty window [lo, hi) offers QPR pivots at evenly spaced
+// positions; for every pivot every lane counts, inside its own run's window,
+// the elements that precede the pivot (binary search, M searches per lane).
+// The clamped counts sum to less than `a` exactly when the pivot is among the
+// first `a` elements, and each decided pivot moves lo or hi of every run.
+// Every round strictly shrinks every non-empty window, so the loop ends with
+// lo = hi = the split.
+template <typename K, int F, int M>
+__device__ inline u64 wave_select(const K* __restrict__ src, u64 roff, u64 rlen, u64 total, u64 a,
+                                  u32* counters) {
+  constexpr int NPIV = 64 * M / F;
+  constexpr int QPR = NPIV / F;
+  static_assert(QPR >= 1, "every run needs a pivot per round");
+  const u32 lane = threadIdx.x & 63;
+  const u32 r = lane % F;
+  u64 lo = a + rlen > total ? a + rlen - total : 0;
+  u64 hi = a < rlen ? a : rlen;
+  for (int round = 0; round < 96; ++round) {
+    if (__ballot(lo < hi) == 0) return lo;
+    u64 nlo = lo, nhi = hi;
+    u64 pos[M], slo[M], shi[M];
+    K px[M];
+    bool pvalid[M];
+    u32 own[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const u32 s = lane + 64 * m;
+      const u32 piv = s / F;
+      own[m] = piv % F;
+      const u32 qi = piv / F;
+      const u64 lo_o = __shfl(lo, (int)own[m]);
+      const u64 hi_o = __shfl(hi, (int)own[m]);
+      const u64 off_o = __shfl(roff, (int)own[m]);
+      const u64 W = hi_o - lo_o;
+      pvalid[m] = W > 0;
+      pos[m] = lo_o + (W * (qi + 1)) / (QPR + 1);
+      px[m] = pvalid[m] ? src[off_o + pos[m]] : (K)0;
+      slo[m] = lo;
+      shi[m] = hi;
+    }
+    // M interleaved binary searches in this lane's run window
+    bool any = true;
+    while (any) {
+      any = false;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if (slo[m] < shi[m] && own[m] != r) {
+          const u64 mid = slo[m] + ((shi[m] - slo[m]) >> 1);
+          const K v = src[roff + mid];
+          const bool right = (r < own[m]) ? (v <= px[m]) : (v < px[m]);
+          if (right) slo[m] = mid + 1; else shi[m] = mid;
+          any = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const u64 c = (own[m] == r) ? pos[m] : slo[m];
+      u64 tot = c;
+#pragma unroll
+      for (int o = 1; o < F; o <<= 1) tot += __shfl_xor(tot, o);
+      if (pvalid[m]) {
+        if (tot < a) {
+          const u64 cand = (own[m] == r) ? pos[m] + 1 : c;
+          nlo = cand > nlo ? cand : nlo;
+        } else {
+          const u64 cand = c;
+          nhi = cand < nhi ? cand : nhi;
+        }
+      }
+    }
+#pragma unroll
+    for (int o = F; o < 64; o <<= 1) {
+      const u64 ol = __shfl_xor(nlo, o), oh = __shfl_xor(nhi, o);
+      nlo = ol > nlo ? ol : nlo;
+      nhi = oh < nhi ? oh : nhi;
+    }
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) set_error(counters, E_SELECT);
+  return lo;
+}
+
+template <typename K, int F, int M>
+__global__ __launch_bounds__(256) void k_partition(Plan p, Level L, const K* __restrict__ src) {
+  const u32 q = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const u32 lane = threadIdx.x & 63;
+  const u32 total_tiles = p.mtile[L.NG];
+  if (q >= total_tiles + L.NG) return;
+  // group g owns boundary slots [mtile[g] + g, mtile[g+1] + g + 1)
+  u32 lo = 0, hi = L.NG;
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if (p.mtile[mid] + mid <= q) lo = mid; else hi = mid;
+  }
+  const u32 g = lo;
+  const u32 t = q - (p.mtile[g] + g);
+  const u32 nt = p.mtile[g + 1] - p.mtile[g];
+  if (t > nt) return;
+  u64 goff, glen;
+  group_info(p, L, g, goff, glen);
+  u64 roff = 0, rlen = 0;
+  if (lane < (u32)F) run_info(p, L, g, lane, roff, rlen);
+  roff = __shfl(roff, (int)(lane % F));
+  rlen = __shfl(rlen, (int)(lane % F));
+  const u64 a = (u64)t * p.TM < glen ? (u64)t * p.TM : glen;
+  u64 cut;
+  if (a == 0) cut = 0;
+  else if (a == glen) cut = rlen;
+  else cut = wave_select<K, F, M>(src, roff, rlen, glen, a, p.counters);
+  if (lane < (u32)F) p.mcut[(u64)q * F + lane] = cut;
+}
+
+// ----------------------------------------------------------------- merge tile
+template <typename K, bool HASV, int F, int TM>
+__global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restrict__ src,
+                                               const u32* __restrict__ srcv, K* __restrict__ dst,
+                                               u32* __restrict__ dstv) {
+  constexpr int NT = 256, IT = TM / NT;
+  __shared__ K s_k[2][TM];
+  __shared__ uint16_t s_i[2][TM];
+  __shared__ u32 s_v[HASV ? TM : 1];
+  __shared__ u64 s_roff[F];
+  __shared__ u32 s_so[F + 1];
+  __shared__ u64 s_out;
+  const u32 tid = threadIdx.x;
+  const u32 tile = blockIdx.x;
+  if (tile >= p.mtile[L.NG]) return;
+  if (tid == 0) {
+    const u32 g = find_seg(p.mtile, L.NG, tile);
+    const u32 t = tile - p.mtile[g];
+    const u64 q0 = (u64)p.mtile[g] + g + t;
+    u64 goff, glen;
+    group_info(p, L, g, goff, glen);
+    // Cuts are clamped into their runs and the tile into its group so that a
+    // wrong split could never address memory outside the buffers.
+    u64 acc = 0;
+    for (int r = 0; r < F; ++r) {
+      u64 off, len;
+      run_info(p, L, g, r, off, len);
+      u64 c0 = p.mcut[q0 * F + r], c1 = p.mcut[(q0 + 1) * F + r];
+      c0 = c0 < len ? c0 : len;
+      c1 = c1 < c0 ? c0 : (c1 < len ? c1 : len);
+      s_roff[r] = off + c0;
+      s_so[r] = (u32)(acc < (u64)TM ? acc : (u64)TM);
+      acc += c1 - c0;
+    }
+    const u64 room = glen - (u64)t * TM;
+    s_so[F] = (u32)(acc < room ? (acc < (u64)TM ? acc : (u64)TM) : (room < (u64)TM ? room : (u64)TM));
+    s_out = goff + (u64)t * TM;
+  }
+  __syncthreads();
+  const u32 n = s_so[F] < (u32)TM ? s_so[F] : (u32)TM;
+  for (u32 q = tid; q < n; q += NT) {
+    u32 r = 0;
+#pragma unroll
+    for (int x = 1; x < F; ++x) r += (q >= s_so[x]) ? 1u : 0u;
+    const u64 e = s_roff[r] + (q - s_so[r]);
+    s_k[0][q] = src[e];
+    s_i[0][q] = (uint16_t)q;
+    if (HASV) s_v[q] = srcv[e];
+  }
+  __syncthreads();
+  int cur = 0;
+#pragma unroll
+  for (int w = 1; w < F; w <<= 1) {
+    const K* ck = s_k[cur];
+    const uint16_t* ci = s_i[cur];
+    K* nk = s_k[cur ^ 1];
+    uint16_t* ni = s_i[cur ^ 1];
+    u32 q = tid * IT;
+    const u32 qend = q + IT < n ? q + IT : n;
+    while (q < qend) {
+      // the pair of lists (each `w` segments long) that holds output q
+      u32 j = 0;
+#pragma unroll
+      for (int x = 2 * w; x < F; x += 2 * w) j += (q >= s_so[x]) ? 1u : 0u;
+      const u32 a0 = s_so[2 * j * w];
+      const u32 a1 = s_so[min((u32)((2 * j + 1) * w), (u32)F)];
+      const u32 b1 = s_so[min((u32)((2 * j + 2) * w), (u32)F)];
+      const u32 la = a1 - a0, lb = b1 - a1;
+      const u32 diag = q - a0;
+      u32 lo = diag > lb ? diag - lb : 0, hi = diag < la ? diag : la;
+      while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (ck[a0 + mid] <= ck[a1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
+      }
+      u32 ia = a0 + lo, ib = a1 + diag - lo;
+      const u32 sub_end = qend < b1 ? qend : b1;
+      for (; q < sub_end; ++q) {
+        const bool takeA = ib >= b1 || (ia < a1 && ck[ia] <= ck[ib]);
+        if (takeA) {
+          nk[q] = ck[ia];
+          ni[q] = ci[ia];
+          ++ia;
+        } else {
+          nk[q] = ck[ib];
+          ni[q] = ci[ib];
+          ++ib;
+        }
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const u64 out = s_out;
+  for (u32 q = tid; q < n; q += NT) {
+    dst[out + q] = s_k[cur][q];
+    if (HASV) dstv[out + q] = s_v[s_i[cur][q]];
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+template <typename K, bool HASV, int F, int TM>
+static void run_level(const Plan& p, const Level& L, const K* src, const u32* srcv, K* dst, u32* dstv,
+                      u64 max_tiles, hipStream_t s) {
+  constexpr int M = F <= 4 ? 1 : (F == 8 ? 2 : 4);
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_merge_plan, dim3(1), dim3(1024), 0, s, p, L); prof_end(pe_, "merge_plan", s); }
+  const u64 slots = max_tiles + L.NG + 1;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition", s); }
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_merge<K, HASV, F, TM>), dim3((u32)max_tiles), dim3(256), 0, s, p, L, src, srcv, dst,
+                     dstv); prof_end(pe_, "merge", s); }
+}
+
+template <typename K, bool HASV, int F>
+static void run_level_tm(const Plan& p, const Level& L, const K* src, const u32* srcv, K* dst, u32* dstv,
+                         u64 max_tiles, hipStream_t s) {
+  switch (p.TM) {
+    case 1024: run_level<K, HASV, F, 1024>(p, L, src, srcv, dst, dstv, max_tiles, s); break;
+    case 4096: run_level<K, HASV, F, 4096>(p, L, src, srcv, dst, dstv, max_tiles, s); break;
+    default: run_level<K, HASV, F, 2048>(p, L, src, srcv, dst, dstv, max_tiles, s); break;
+  }
+}
+
+// One handler pass.  max_tiles bounds the pass's tile count (total_n/TM + groups).
+template <typename K, bool HASV>
+void launch_merge_level(const Plan& p, u32 level, const K* src, const u32* srcv, K* dst, u32* dstv,
+                        hipStream_t s) {
+  Level L;
+  L.level = level;
+  L.RS = 1;
+  for (u32 x = 0; x < level; ++x) L.RS *= p.F;
+  L.GS = L.RS * p.F;
+  L.Q = (p.P + L.GS - 1) / L.GS;
+  L.NG = p.B * p.P * L.Q;
+  const u64 max_tiles = p.total_n / p.TM + L.NG;
+  if (max_tiles == 0) return;
+  switch (p.F) {
+    case 2: run_level_tm<K, HASV, 2>(p, L, src, srcv, dst, dstv, max_tiles, s); break;
+    case 4: run_level_tm<K, HASV, 4>(p, L, src, srcv, dst, dstv, max_tiles, s); break;
+    case 16: run_level_tm<K, HASV, 16>(p, L, src, srcv, dst, dstv, max_tiles, s); break;
+    default: run_level_tm<K, HASV, 8>(p, L, src, srcv, dst, dstv, max_tiles, s); break;
+  }
+}
+
+template void launch_merge_level<u32, false>(const Plan&, u32, const u32*, const u32*, u32*, u32*, hipStream_t);
+template void launch_merge_level<u32, true>(const Plan&, u32, const u32*, const u32*, u32*, u32*, hipStream_t);
+template void launch_merge_level<u64, false>(const Plan&, u32, const u64*, const u32*, u64*, u32*, hipStream_t);
+template void launch_merge_level<u64, true>(const Plan&, u32, const u64*, const u32*, u64*, u32*, hipStream_t);
+
+}  // namespace lbs

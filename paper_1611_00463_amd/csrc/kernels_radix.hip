@@ -1,0 +1,426 @@
+// Step 1 of Section IV on the GPU: every block (virtual processor) is sorted
+// on its own by a stable least-significant-digit radix sort (the paper names
+// radix sort in Section II; its own step 1 uses quicksort, which is not
+// stable).  One pass per 8-bit digit.  Each pass is a single kernel in the
+// "onesweep" style (Adinets and Merrill, 2022): per-block digit counts of all
+// passes are taken up front, and a tile finds where its keys go from the
+// running counts of the earlier tiles of the same block, published through a
+// decoupled look-back chain with ordered tile ids.
+//
+// Ranking inside a tile uses wave-wide ballots on the 8 digit bits (a
+// match-any), mbcnt for the rank among equal digits, and per-wave counters in
+// LDS; keys are then staged in LDS in digit order so that the global writes
+// are runs of consecutive addresses.
+#include "lbsort_internal.hpp"
+
+namespace lbs {
+
+constexpr u32 SPIN_LIMIT = 1u << 22;
+
+// ----------------------------------------------------------------- scans
+template <int NT>
+__device__ inline u64 block_exclusive_scan(u64 v, u64* s_w, u64& total) {
+  const u32 lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NWV = NT / 64;
+  u64 x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    u64 y = __shfl_up(x, o);
+    if (lane >= (u32)o) x += y;
+  }
+  if (lane == 63) s_w[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    u64 t = lane < NWV ? s_w[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < NWV; o <<= 1) {
+      u64 y = __shfl_up(t, o);
+      if (lane >= (u32)o) t += y;
+    }
+    if (lane < NWV) s_w[lane] = t;
+  }
+  __syncthreads();
+  u64 wprefix = w ? s_w[w - 1] : 0;
+  total = s_w[NWV - 1];
+  __syncthreads();
+  return wprefix + x - v;
+}
+
+// ----------------------------------------------------------------- plan
+// One workgroup: block starts, radix tile prefix, list of blocks small enough
+// to be sorted whole in LDS, and sample offsets, for every block of every
+// instance.  A malformed segment table latches E_SEG and every block is
+// treated as empty so that no later kernel reads out of range.
+__global__ __launch_bounds__(1024) void k_plan(Plan p) {
+  __shared__ u64 s_w[16];
+  __shared__ u32 s_bad;
+  const u32 tid = threadIdx.x;
+  if (tid == 0) s_bad = (p.seg[0] != 0 || p.seg[p.B] != p.total_n) ? 1u : 0u;
+  __syncthreads();
+  for (u32 b = tid; b < p.B; b += 1024)
+    if (p.seg[b + 1] < p.seg[b]) s_bad = 1u;
+  __syncthreads();
+  const bool bad = s_bad != 0;
+  if (bad && tid == 0) set_error(p.counters, E_SEG);
+  u64 carry_t = 0, carry_s = 0, carry_m = 0;
+  for (u32 base = 0; base < p.NB; base += 1024) {
+    const u32 idx = base + tid;
+    u64 n = 0, bs = 0;
+    if (idx < p.NB) {
+      const u32 b = idx / p.P, i = idx % p.P;
+      if (!bad) {
+        bs = block_begin(p.seg, b, i, p.P);
+        n = block_begin(p.seg, b, i + 1, p.P) - bs;
+      }
+      if (n >= (1ull << 32)) {
+        set_error(p.counters, E_RANGE);
+        n = 0;
+      }
+      p.blk_start[idx] = bs;
+    }
+    const u64 tiles = n > (u64)SORT_TILE ? (n + SORT_TILE - 1) / SORT_TILE : 0;
+    const u64 smp = n < (u64)p.s ? n : (u64)p.s;
+    const u64 small = (n > 0 && n <= (u64)SORT_TILE) ? 1 : 0;
+    u64 tot;
+    u64 ex = block_exclusive_scan<1024>(tiles, s_w, tot);
+    if (idx < p.NB) p.tstart[idx] = (u32)(carry_t + ex);
+    carry_t += tot;
+    ex = block_exclusive_scan<1024>(smp, s_w, tot);
+    if (idx < p.NB) p.samp_start[idx] = carry_s + ex;
+    carry_s += tot;
+    ex = block_exclusive_scan<1024>(small, s_w, tot);
+    if (small) p.small_list[carry_m + ex] = idx;
+    carry_m += tot;
+  }
+  if (tid == 0) {
+    p.tstart[p.NB] = (u32)carry_t;
+    p.samp_start[p.NB] = carry_s;
+    p.blk_start[p.NB] = bad ? 0 : p.seg[p.B];
+    p.counters[C_NSMALL] = (u32)carry_m;
+  }
+}
+
+__global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) a[i] = v;
+}
+
+// ----------------------------------------------------------------- histogram
+// Digit counts of all passes for every tile of a large block, accumulated per
+// block.  Equal keys inside a wave are first merged (a few leader rounds) so
+// that heavy duplicates do not serialise on one LDS counter.
+template <typename K>
+__global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ src) {
+  constexpr int D = KeyT<K>::BITS / RADIX_BITS;
+  __shared__ u32 h[D * RADIX];
+  __shared__ u32 s_blk;
+  const u32 tid = threadIdx.x, lane = tid & 63;
+  const u32 t = blockIdx.x;
+  const u32 total = p.tstart[p.NB];
+  if (t >= total) return;
+  for (int i = tid; i < D * RADIX; i += SORT_NT) h[i] = 0;
+  if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t);
+  __syncthreads();
+  const u32 blk = s_blk;
+  const u64 tbase = p.blk_start[blk] + (u64)(t - p.tstart[blk]) * SORT_TILE;
+  const u64 rem = p.blk_start[blk + 1] - tbase;
+  const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+#pragma unroll 4
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const u32 idx = j * SORT_NT + tid;
+    const bool valid = idx < tile_n;
+    const K key = valid ? src[tbase + idx] : (K)0;
+    bool done = !valid;
+    for (int r = 0; r < 3; ++r) {
+      const u64 act = __ballot(!done);
+      if (act == 0) break;
+      const int leader = __ffsll((unsigned long long)act) - 1;
+      const K lk = __shfl(key, leader);
+      const bool same = !done && key == lk;
+      const u64 sm = __ballot(same);
+      if (__popcll(sm) < 2) break;  // no duplicate of the leader: leave all to the bulk path
+      if (lane == (u32)leader) {
+        const u32 c = (u32)__popcll(sm);
+#pragma unroll
+        for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((lk >> (q * RADIX_BITS)) & (RADIX - 1))], c);
+      }
+      done = done || same;
+    }
+    if (!done) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1))], 1u);
+    }
+  }
+  __syncthreads();
+  u32* gh = p.hist + (u64)blk * D * RADIX;
+  for (int i = tid; i < D * RADIX; i += SORT_NT)
+    if (h[i]) atomicAdd(&gh[i], h[i]);
+}
+
+// Exclusive scan of the 256 counts of every (block, pass): digit start offsets.
+__global__ __launch_bounds__(256) void k_scan_hist(Plan p) {
+  const u32 gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const u32 lane = threadIdx.x & 63;
+  if (gw >= p.NB * p.D) return;
+  const u32 blk = gw / p.D;
+  if (p.tstart[blk + 1] == p.tstart[blk]) return;
+  u32* h = p.hist + (u64)gw * RADIX;
+  const u32 a0 = h[lane * 4 + 0], a1 = h[lane * 4 + 1], a2 = h[lane * 4 + 2], a3 = h[lane * 4 + 3];
+  const u32 s = a0 + a1 + a2 + a3;
+  u32 x = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    u32 y = __shfl_up(x, o);
+    if (lane >= (u32)o) x += y;
+  }
+  const u32 ex = x - s;
+  h[lane * 4 + 0] = ex;
+  h[lane * 4 + 1] = ex + a0;
+  h[lane * 4 + 2] = ex + a0 + a1;
+  h[lane * 4 + 3] = ex + a0 + a1 + a2;
+}
+
+// ----------------------------------------------------------------- ranking
+// Items are laid out wave-major: item j of lane l of wave w is tile position
+// w*64*ITEMS + j*64 + l, so processing j in order and lanes in order inside a
+// wave keeps the ranking stable.  wc: this wave's 256 digit counters.
+template <typename K, int ITEMS>
+__device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n, u32 shift, u32* wc,
+                                  u32 (&rank)[ITEMS], u32 (&dig)[ITEMS]) {
+  const u32 lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const bool valid = wbase + j * 64 + lane < tile_n;
+    const u32 d = (u32)(keys[j] >> shift) & (RADIX - 1);
+    u64 m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RADIX_BITS; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const u64 bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const u32 below = count_below(m);
+    u32 base = 0;
+    if (valid) base = wc[d];
+    if (valid && below == 0) wc[d] = base + (u32)__popcll(m);
+    rank[j] = base + below;
+    dig[j] = d;
+  }
+}
+
+// ----------------------------------------------------------------- one pass
+template <typename K, bool HASV>
+__global__ __launch_bounds__(SORT_NT) void k_onesweep(Plan p, const K* __restrict__ src,
+                                                      const u32* __restrict__ srcv, K* __restrict__ dst,
+                                                      u32* __restrict__ dstv, u32 pass) {
+  constexpr int NWV = SORT_NT / 64, WI = 64 * SORT_ITEMS;
+  static_assert(SORT_NT == RADIX, "one thread per digit");
+  __shared__ u32 s_wc[NWV][RADIX];
+  __shared__ u64 s_gbase[RADIX];
+  __shared__ u32 s_lstart[RADIX];
+  __shared__ u64 s_scan[NWV];
+  __shared__ K s_keys[SORT_TILE];
+  __shared__ u32 s_vals[HASV ? SORT_TILE : 1];
+  __shared__ u32 s_info[2];
+  const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const u32 shift = pass * RADIX_BITS;
+  const u32 total = p.tstart[p.NB];
+  if (tid == 0) {
+    const u32 t = atomicAdd(&p.counters[C_TILE0 + pass], 1u);
+    s_info[0] = t;
+    s_info[1] = t < total ? find_seg(p.tstart, p.NB, t) : 0u;
+  }
+  for (int i = tid; i < NWV * RADIX; i += SORT_NT) (&s_wc[0][0])[i] = 0;
+  __syncthreads();
+  const u32 t = s_info[0];
+  if (t >= total) return;
+  const u32 blk = s_info[1];
+  const u32 lt = t - p.tstart[blk];
+  const u64 bstart = p.blk_start[blk];
+  const u64 tbase = bstart + (u64)lt * SORT_TILE;
+  const u64 rem = p.blk_start[blk + 1] - tbase;
+  const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+  const u32 wbase = w * WI;
+
+  K keys[SORT_ITEMS];
+  u32 vals[HASV ? SORT_ITEMS : 1];
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const u32 idx = wbase + j * 64 + lane;
+    if (idx < tile_n) {
+      keys[j] = src[tbase + idx];
+      if (HASV) vals[j] = srcv[tbase + idx];
+    } else {
+      keys[j] = 0;
+      if (HASV) vals[j] = 0;
+    }
+  }
+  u32 rank[SORT_ITEMS], dig[SORT_ITEMS];
+  rank_items<K, SORT_ITEMS>(keys, wbase, tile_n, shift, s_wc[w], rank, dig);
+  __syncthreads();
+
+  // Per-digit tile count; per-wave counters become exclusive wave prefixes.
+  u32 tot = 0;
+#pragma unroll
+  for (int v = 0; v < NWV; ++v) {
+    const u32 c = s_wc[v][tid];
+    s_wc[v][tid] = tot;
+    tot += c;
+  }
+  // Decoupled look-back over the earlier tiles of this block, digit = tid.
+  const u32 epoch = pass + 1;
+  u64* st = p.status + (u64)t * RADIX + tid;
+  u64 excl = 0;
+  if (lt == 0) {
+    st_release_agent(st, st_pack(epoch, ST_INC, tot));
+  } else {
+    st_release_agent(st, st_pack(epoch, ST_AGG, tot));
+    u32 pt = t - 1, spins = 0;
+    while (true) {
+      const u64 v = ld_acquire_agent(p.status + (u64)pt * RADIX + tid);
+      if ((u32)(v >> 56) != epoch) {
+        if (++spins > SPIN_LIMIT) {
+          set_error(p.counters, E_SPIN);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += v & ST_VALMASK;
+      if (((v >> 54) & 3u) == ST_INC) break;
+      --pt;
+    }
+    st_release_agent(st, st_pack(epoch, ST_INC, excl + tot));
+  }
+  u64 ttot;
+  const u32 lstart = (u32)block_exclusive_scan<SORT_NT>(tot, s_scan, ttot);
+  s_lstart[tid] = lstart;
+  s_gbase[tid] = bstart + p.hist[((u64)blk * p.D + pass) * RADIX + tid] + excl - lstart;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    if (wbase + j * 64 + lane < tile_n) {
+      const u32 pos = s_lstart[dig[j]] + s_wc[w][dig[j]] + rank[j];
+      s_keys[pos] = keys[j];
+      if (HASV) s_vals[pos] = vals[j];
+    }
+  }
+  __syncthreads();
+  for (u32 i = tid; i < tile_n; i += SORT_NT) {
+    const K k = s_keys[i];
+    const u64 o = s_gbase[(u32)(k >> shift) & (RADIX - 1)] + i;
+    dst[o] = k;
+    if (HASV) dstv[o] = s_vals[i];
+  }
+}
+
+// ----------------------------------------------------------------- small blocks
+// A block of at most one tile is sorted entirely in LDS: all digit passes,
+// no look-back, one read and one write of global memory.
+template <typename K, bool HASV>
+__global__ __launch_bounds__(SORT_NT) void k_small_sort(Plan p, const K* __restrict__ src,
+                                                        const u32* __restrict__ srcv, K* __restrict__ dst,
+                                                        u32* __restrict__ dstv) {
+  constexpr int NWV = SORT_NT / 64, WI = 64 * SORT_ITEMS;
+  constexpr int D = KeyT<K>::BITS / RADIX_BITS;
+  __shared__ u32 s_wc[NWV][RADIX];
+  __shared__ u32 s_lstart[RADIX];
+  __shared__ u64 s_scan[NWV];
+  __shared__ K s_keys[SORT_TILE];
+  __shared__ u32 s_vals[HASV ? SORT_TILE : 1];
+  const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (blockIdx.x >= p.counters[C_NSMALL]) return;
+  const u32 blk = p.small_list[blockIdx.x];
+  const u64 bstart = p.blk_start[blk];
+  const u32 n = (u32)(p.blk_start[blk + 1] - bstart);
+  const u32 wbase = w * WI;
+  K keys[SORT_ITEMS];
+  u32 vals[HASV ? SORT_ITEMS : 1];
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const u32 idx = wbase + j * 64 + lane;
+    keys[j] = idx < n ? src[bstart + idx] : (K)0;
+    if (HASV) vals[j] = idx < n ? srcv[bstart + idx] : 0u;
+  }
+  for (int pass = 0; pass < D; ++pass) {
+    const u32 shift = pass * RADIX_BITS;
+    for (int i = tid; i < NWV * RADIX; i += SORT_NT) (&s_wc[0][0])[i] = 0;
+    __syncthreads();
+    u32 rank[SORT_ITEMS], dig[SORT_ITEMS];
+    rank_items<K, SORT_ITEMS>(keys, wbase, n, shift, s_wc[w], rank, dig);
+    __syncthreads();
+    u32 tot = 0;
+#pragma unroll
+    for (int v = 0; v < NWV; ++v) {
+      const u32 c = s_wc[v][tid];
+      s_wc[v][tid] = tot;
+      tot += c;
+    }
+    u64 ttot;
+    s_lstart[tid] = (u32)block_exclusive_scan<SORT_NT>(tot, s_scan, ttot);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      if (wbase + j * 64 + lane < n) {
+        const u32 pos = s_lstart[dig[j]] + s_wc[w][dig[j]] + rank[j];
+        s_keys[pos] = keys[j];
+        if (HASV) s_vals[pos] = vals[j];
+      }
+    }
+    __syncthreads();
+    if (pass + 1 < D) {
+#pragma unroll
+      for (int j = 0; j < SORT_ITEMS; ++j) {
+        const u32 idx = wbase + j * 64 + lane;
+        keys[j] = idx < n ? s_keys[idx] : (K)0;
+        if (HASV) vals[j] = idx < n ? s_vals[idx] : 0u;
+      }
+      __syncthreads();
+    }
+  }
+  for (u32 i = tid; i < n; i += SORT_NT) {
+    dst[bstart + i] = s_keys[i];
+    if (HASV) dstv[bstart + i] = s_vals[i];
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+void launch_plan(const Plan& p, hipStream_t s) { { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, p); prof_end(pe_, "plan", s); } }
+
+void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s) {
+  if (n == 0) return;
+  u64 blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_fill32, dim3((u32)blocks), dim3(256), 0, s, a, n, v); prof_end(pe_, "fill", s); }
+}
+
+template <typename K>
+void launch_hist(const Plan& p, const K* src, hipStream_t s) {
+  if (p.max_tiles == 0) return;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_hist<K>, dim3(p.max_tiles), dim3(SORT_NT), 0, s, p, src); prof_end(pe_, "hist", s); }
+  const u32 waves = p.NB * p.D;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_scan_hist, dim3((waves + 3) / 4), dim3(256), 0, s, p); prof_end(pe_, "scan_hist", s); }
+}
+
+template <typename K, bool HASV>
+void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s) {
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_small_sort<K, HASV>), dim3(p.NB), dim3(SORT_NT), 0, s, p, src, srcv, dst, dstv); prof_end(pe_, "small_sort", s); }
+}
+
+template <typename K, bool HASV>
+void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s) {
+  if (p.max_tiles == 0) return;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV>), dim3(p.max_tiles), dim3(SORT_NT), 0, s, p, src, srcv, dst, dstv,
+                     pass); prof_end(pe_, "onesweep", s); }
+}
+
+#define LBS_INST(K)                                                                                     \
+  template void launch_hist<K>(const Plan&, const K*, hipStream_t);                                   \
+  template void launch_small_sort<K, false>(const Plan&, const K*, const u32*, K*, u32*, hipStream_t); \
+  template void launch_small_sort<K, true>(const Plan&, const K*, const u32*, K*, u32*, hipStream_t);  \
+  template void launch_onesweep<K, false>(const Plan&, const K*, const u32*, K*, u32*, u32, hipStream_t); \
+  template void launch_onesweep<K, true>(const Plan&, const K*, const u32*, K*, u32*, u32, hipStream_t);
+LBS_INST(u32)
+LBS_INST(u64)
+#undef LBS_INST
+
+}  // namespace lbs

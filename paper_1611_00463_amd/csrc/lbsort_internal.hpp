@@ -1,0 +1,136 @@
+// Internal definitions shared by the kernels and the engine of lbsort.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbs {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+// Radix sort geometry (step 1): 8-bit digits, tiles of NT threads x ITEMS keys.
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int SORT_NT = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_NT * SORT_ITEMS;  // 4096 keys per tile
+constexpr int WAVE = 64;
+
+// Look-back status word: [63:56] epoch (pass + 1), [55:54] flag, [53:0] count.
+constexpr u64 ST_AGG = 1, ST_INC = 2;
+constexpr u64 ST_VALMASK = (1ull << 54) - 1;
+__host__ __device__ inline u64 st_pack(u32 epoch, u64 flag, u64 v) {
+  return ((u64)epoch << 56) | (flag << 54) | (v & ST_VALMASK);
+}
+
+// Slots of the small counter array at the head of the workspace.
+enum Counter : int {
+  C_ERR = 0,        // device error bits (sticky until lbsort_check)
+  C_NSMALL = 1,     // number of blocks sorted whole in LDS
+  C_TILE0 = 2,      // C_TILE0 + pass: ordered tile ids of radix pass `pass`
+  C_COUNT = 32
+};
+enum DevErr : u32 {
+  E_SPIN = 1u,         // a decoupled look-back wait gave up
+  E_SEG = 2u,          // malformed segment table
+  E_SELECT = 4u,       // merge-path selection did not converge
+  E_RANGE = 8u         // an instance or block too large for 32-bit counters
+};
+
+// Everything a kernel needs to know about one call, passed by value.
+struct Plan {
+  u32 B, P, NB;          // instances, processors, blocks = B * P
+  u32 s;                 // samples per block (before capping by block size)
+  u32 D;                 // radix passes = key bits / 8
+  u32 inv;               // investigator mode
+  u32 F, L, TM;          // merge fan-in, merge levels, merge tile
+  u32 max_tiles;         // radix tiles, worst case
+  u64 total_n;
+  const u64* seg;        // [B+1]
+  u64* blk_start;        // [NB+1]
+  u32* tstart;           // [NB+1] radix tile prefix (blocks larger than one tile)
+  u32* small_list;       // [NB]
+  u32* counters;         // [C_COUNT]
+  u32* hist;             // [NB][D][256]
+  u64* status;           // [max_tiles][256]
+  u64* samp_start;       // [NB+1]
+  void* samples;         // [<= NB*s] keys
+  void* pool;            // [<= NB*s] keys, sample pool sorted per instance
+  u64* lo;               // [B][P][P-1]
+  u64* hi;               // [B][P][P-1]
+  u64* cuts;             // [B][P][P+1]
+  u64* Dm;               // [B][P+1][P] receive offsets, row P = G_{k+1}
+  u64* G;                // [B][P+1]
+  void* splitters;       // [B][P-1]
+  u32* mtile;            // [NGmax+1] merge tile prefix of the current level
+  u64* mcut;             // [slots][F] merge tile boundary cuts
+  u32 ng_max;            // merge groups, worst case over levels
+  u32 mslots_max;        // merge boundary slots, worst case
+};
+
+// ----------------------------------------------------------------- helpers
+template <typename K>
+struct KeyT;
+template <>
+struct KeyT<u32> {
+  static constexpr int BITS = 32;
+  static constexpr u32 MAXV = 0xFFFFFFFFu;
+};
+template <>
+struct KeyT<u64> {
+  static constexpr int BITS = 64;
+  static constexpr u64 MAXV = ~0ull;
+};
+
+__device__ inline u32 lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+// Number of set bits of `mask` in lanes below the calling lane.
+__device__ inline u32 count_below(u64 mask) {
+  return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0));
+}
+
+__device__ inline void set_error(u32* counters, u32 bits) { atomicOr(&counters[C_ERR], bits); }
+
+__device__ inline u64 ld_acquire_agent(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_release_agent(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Largest b in [0, n) with prefix[b] <= t (prefix non-decreasing, prefix[0] = 0).
+template <typename T>
+__device__ inline u32 find_seg(const T* prefix, u32 n, u64 t) {
+  u32 lo = 0, hi = n;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    u32 mid = (lo + hi) >> 1;
+    if ((u64)prefix[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Number of elements of sorted a[0, n) that are < x (lower) or <= x (upper).
+template <typename K, bool UPPER>
+__device__ inline u64 bsearch_count(const K* a, u64 lo, u64 hi, K x) {
+  while (lo < hi) {
+    u64 mid = lo + ((hi - lo) >> 1);
+    K v = a[mid];
+    bool go_right = UPPER ? (v <= x) : (v < x);
+    if (go_right) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Block of instance b, processor i: start = seg[b] + floor(i * n_b / P).
+__device__ inline u64 block_begin(const u64* seg, u32 b, u32 i, u32 P) {
+  u64 a = seg[b], n = seg[b + 1] - seg[b];
+  return a + (u64)(((unsigned __int128)i * n) / P);
+}
+
+// Optional per-launch event timing (lbsort_profile_enable).
+int prof_begin(hipStream_t s);
+void prof_end(int id, const char* name, hipStream_t s);
+
+}  // namespace lbs

@@ -1,0 +1,235 @@
+"""Thin Python binding of the lbsort C ABI (ctypes over ``_lib/liblbsort.so``).
+
+Argument marshalling only: every step of the sort runs in the HIP library.
+Tensors are torch CUDA (ROCm) tensors used as raw device storage; the calls
+are enqueued on torch's current stream.  If the library has not been built,
+every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "liblbsort.so")
+
+U32, U64 = 1, 2
+NOVAL, VAL_U32 = 0, 1
+INV_COUNT, INV_NONE, INV_PAPER = 0, 1, 2
+OK = 0
+ERR_INVALID_ARG, ERR_WORKSPACE_TOO_SMALL, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_DEVICE = -1, -2, -3, -4, -5, -6
+
+_c_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_uint32), ("s", ctypes.c_uint32), ("investigator", ctypes.c_uint32),
+                ("fanin", ctypes.c_uint32), ("merge_tile", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Parts(ctypes.Structure):
+    _fields_ = [("part_offsets", ctypes.c_void_p), ("part_counts", ctypes.c_void_p),
+                ("splitters", ctypes.c_void_p), ("send_counts", ctypes.c_void_p),
+                ("cuts", ctypes.c_void_p)]
+
+
+EXPORTS = ("lbsort_sort_keys", "lbsort_sort_pairs", "lbsort_sort_batch", "lbsort_local_sort",
+           "lbsort_check", "lbsort_status_string", "lbsort_last_error", "lbsort_autotune",
+           "lbsort_load_tuning")
+
+_lib = None
+
+
+class LbsortError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbsort error {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"lbsort HIP library not built ({path}); run paper_1611_00463_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, u32, u64, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)
+    pp, pa = ctypes.POINTER(Params), ctypes.POINTER(Parts)
+    lib.lbsort_sort_keys.argtypes = [i32, vp, vp, u64, pp, pa, vp, sz, vp]
+    lib.lbsort_sort_pairs.argtypes = [i32, i32, vp, vp, vp, vp, u64, pp, pa, vp, sz, vp]
+    lib.lbsort_sort_batch.argtypes = [i32, i32, vp, vp, vp, vp, vp, u32, u64, pp, pa, vp, sz, vp]
+    lib.lbsort_local_sort.argtypes = [i32, i32, vp, vp, vp, vp, vp, u32, u64, pp, vp, sz, vp]
+    lib.lbsort_check.argtypes = [vp, vp]
+    lib.lbsort_status_string.argtypes = [i32]
+    lib.lbsort_status_string.restype = ctypes.c_char_p
+    lib.lbsort_last_error.restype = ctypes.c_char_p
+    lib.lbsort_autotune.argtypes = [i32, i32, u64, u32, u32, ctypes.c_char_p, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+    lib.lbsort_load_tuning.argtypes = [ctypes.c_char_p]
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
+    lib.lbsort_status_string.restype = ctypes.c_char_p
+    lib.lbsort_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        lib = load()
+        raise LbsortError(rc, f"{lib.lbsort_status_string(rc).decode()}: {lib.lbsort_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def key_code(dtype) -> int:
+    if dtype == torch.uint64:
+        return U64
+    if dtype == torch.uint32:
+        return U32
+    raise TypeError(f"keys must be torch.uint64 or torch.uint32, got {dtype}")
+
+
+@dataclass
+class SortResult:
+    keys: torch.Tensor
+    vals: torch.Tensor | None
+    part_offsets: torch.Tensor      # [B, P+1] (uint64 as int64 storage)
+    part_counts: torch.Tensor       # [B, P]
+    splitters: torch.Tensor         # [B, P-1]
+    send_counts: torch.Tensor | None
+    cuts: torch.Tensor | None
+    workspace: torch.Tensor
+
+
+class Workspace:
+    """A reusable device workspace that grows on demand."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def _params(P, s, investigator, fanin, merge_tile):
+    return Params(P, s, investigator, fanin, merge_tile, 0)
+
+
+def _alloc_parts(B, P, kdt, device, want_send, want_cuts):
+    offs = torch.empty((B, P + 1), dtype=torch.int64, device=device)
+    counts = torch.empty((B, P), dtype=torch.int64, device=device)
+    spl = torch.empty((B, max(P - 1, 0)), dtype=kdt, device=device)
+    send = torch.empty((B, P, P), dtype=torch.int64, device=device) if want_send else None
+    cuts = torch.empty((B, P, P + 1), dtype=torch.int64, device=device) if want_cuts else None
+    parts = Parts(offs.data_ptr(), counts.data_ptr(), spl.data_ptr() if P > 1 else None,
+                  send.data_ptr() if send is not None else None, cuts.data_ptr() if cuts is not None else None)
+    return parts, offs, counts, spl, send, cuts
+
+
+def _run(fn, args_before_ws, ws: Workspace | None, device):
+    """Two-phase workspace protocol: size query, then the call."""
+    lib = load()
+    need = ctypes.c_size_t(0)
+    _check(fn(*args_before_ws, None, ctypes.byref(need), None))
+    ws = ws or Workspace(device)
+    buf = ws.get(need.value)
+    have = ctypes.c_size_t(buf.numel())
+    _check(fn(*args_before_ws, ctypes.c_void_p(buf.data_ptr()), ctypes.byref(have), _stream()))
+    return buf
+
+
+def sort_batch(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torch.Tensor | None = None,
+               s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0,
+               keys_out=None, vals_out=None, want_send=False, want_cuts=False,
+               workspace: Workspace | None = None) -> SortResult:
+    """lbsort_sort_batch: seg_offsets is a device tensor of B+1 offsets (int64/uint64)."""
+    lib = load()
+    kc = key_code(keys.dtype)
+    B = seg_offsets.numel() - 1
+    n = keys.numel()
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    parts, offs, counts, spl, send, cuts = _alloc_parts(B, P, keys.dtype, keys.device, want_send, want_cuts)
+    prm = _params(P, s, investigator, fanin, merge_tile)
+    args = (kc, VAL_U32 if vals is not None else NOVAL, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
+            _ptr(seg_offsets), B, n, ctypes.byref(prm), ctypes.byref(parts))
+    buf = _run(lib.lbsort_sort_batch, args, workspace, keys.device)
+    return SortResult(keys_out, vals_out, offs, counts, spl, send, cuts, buf)
+
+
+def sort_keys(keys: torch.Tensor, P: int, s: int = 0, investigator: int = INV_COUNT, fanin: int = 0,
+              merge_tile: int = 0, keys_out=None, want_send=False, want_cuts=False,
+              workspace: Workspace | None = None) -> SortResult:
+    """lbsort_sort_keys on one array."""
+    lib = load()
+    kc = key_code(keys.dtype)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    parts, offs, counts, spl, send, cuts = _alloc_parts(1, P, keys.dtype, keys.device, want_send, want_cuts)
+    prm = _params(P, s, investigator, fanin, merge_tile)
+    args = (kc, _ptr(keys), _ptr(keys_out), keys.numel(), ctypes.byref(prm), ctypes.byref(parts))
+    buf = _run(lib.lbsort_sort_keys, args, workspace, keys.device)
+    return SortResult(keys_out, None, offs, counts, spl, send, cuts, buf)
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, P: int, s: int = 0, investigator: int = INV_COUNT,
+               fanin: int = 0, merge_tile: int = 0, keys_out=None, vals_out=None, want_send=False,
+               want_cuts=False, workspace: Workspace | None = None) -> SortResult:
+    """lbsort_sort_pairs on one array of keys with uint32 values."""
+    lib = load()
+    kc = key_code(keys.dtype)
+    if vals.dtype != torch.uint32 or vals.numel() != keys.numel():
+        raise TypeError("vals must be torch.uint32 with one value per key")
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+    parts, offs, counts, spl, send, cuts = _alloc_parts(1, P, keys.dtype, keys.device, want_send, want_cuts)
+    prm = _params(P, s, investigator, fanin, merge_tile)
+    args = (kc, VAL_U32, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), keys.numel(), ctypes.byref(prm),
+            ctypes.byref(parts))
+    buf = _run(lib.lbsort_sort_pairs, args, workspace, keys.device)
+    return SortResult(keys_out, vals_out, offs, counts, spl, send, cuts, buf)
+
+
+def local_sort(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torch.Tensor | None = None,
+               workspace: Workspace | None = None):
+    """lbsort_local_sort: step 1 only, every block sorted on its own."""
+    lib = load()
+    kc = key_code(keys.dtype)
+    B = seg_offsets.numel() - 1
+    keys_out = torch.empty_like(keys)
+    vals_out = torch.empty_like(vals) if vals is not None else None
+    prm = _params(P, 0, INV_COUNT, 0, 0)
+    args = (kc, VAL_U32 if vals is not None else NOVAL, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
+            _ptr(seg_offsets), B, keys.numel(), ctypes.byref(prm))
+    buf = _run(lib.lbsort_local_sort, args, workspace, keys.device)
+    return keys_out, vals_out, buf
+
+
+def check(workspace_buf: torch.Tensor):
+    """lbsort_check: synchronise and raise on a device-side error."""
+    _check(load().lbsort_check(ctypes.c_void_p(workspace_buf.data_ptr()), _stream()))
+
+
+def autotune(key_type: int, val_type: int, n: int, B: int, P: int, cache_path: str | None = None):
+    lib = load()
+    f, t = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    _check(lib.lbsort_autotune(key_type, val_type, n, B, P, cache_path.encode() if cache_path else None,
+                               ctypes.byref(f), ctypes.byref(t)))
+    return f.value, t.value
+
+
+def load_tuning(cache_path: str):
+    _check(load().lbsort_load_tuning(cache_path.encode()))

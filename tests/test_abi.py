@@ -1,0 +1,103 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1611_00463_amd import lbsort as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbsort.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(lbsort_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1611_00463_amd import build
+        build.build()
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared()
+    assert set(names) >= {"lbsort_sort_keys", "lbsort_sort_pairs", "lbsort_sort_batch"}
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(L.EXPORTS) == set(names)
+
+
+def test_status_strings(lib):
+    assert lib.lbsort_status_string(0) == b"ok"
+    assert lib.lbsort_status_string(-2) == b"workspace too small"
+    assert lib.lbsort_status_string(12345) == b"unknown status"
+
+
+def _size(key_type=L.U64, P=8, n=1000, **kw):
+    prm = L.Params(P, kw.get("s", 0), kw.get("inv", 0), kw.get("fanin", 0), kw.get("tile", 0), kw.get("reserved", 0))
+    parts = L.Parts(1, 0, 0, 0, 0)
+    need = ctypes.c_size_t(0)
+    rc = L.load().lbsort_sort_keys(key_type, None, None, n, ctypes.byref(prm), ctypes.byref(parts), None,
+                                   ctypes.byref(need), None)
+    return rc, need.value
+
+
+def test_workspace_query_and_growth(lib):
+    rc, a = _size(n=1 << 20)
+    assert rc == 0 and a > 0
+    rc, b = _size(n=1 << 22)
+    assert rc == 0 and b > a
+    rc, c = _size(n=0)
+    assert rc == 0 and c > 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(key_type=7), L.ERR_INVALID_ARG),
+    (dict(P=0), L.ERR_INVALID_ARG),
+    (dict(P=5000), L.ERR_INVALID_ARG),
+    (dict(inv=9), L.ERR_INVALID_ARG),
+    (dict(fanin=3), L.ERR_INVALID_ARG),
+    (dict(tile=1000), L.ERR_INVALID_ARG),
+    (dict(reserved=1), L.ERR_INVALID_ARG),
+    (dict(s=(1 << 20) + 1), L.ERR_INVALID_ARG),
+    (dict(n=1 << 45), L.ERR_UNSUPPORTED),
+    (dict(P=1, n=1 << 33), L.ERR_UNSUPPORTED),
+])
+def test_rejects_bad_arguments(lib, kw, code):
+    rc, _ = _size(**kw)
+    assert rc == code
+    assert lib.lbsort_last_error()
+
+
+def test_workspace_too_small_and_misaligned(lib):
+    rc, need = _size(n=1 << 16)
+    assert rc == 0
+    prm = L.Params(8, 0, 0, 0, 0, 0)
+    parts = L.Parts(1, 0, 0, 0, 0)
+    small = ctypes.c_size_t(need - 1)
+    rc = lib.lbsort_sort_keys(L.U64, ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), 1 << 16, ctypes.byref(prm),
+                              ctypes.byref(parts), ctypes.c_void_p(1 << 30), ctypes.byref(small), None)
+    assert rc == L.ERR_WORKSPACE_TOO_SMALL
+    big = ctypes.c_size_t(need)
+    rc = lib.lbsort_sort_keys(L.U64, ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), 1 << 16, ctypes.byref(prm),
+                              ctypes.byref(parts), ctypes.c_void_p((1 << 30) + 8), ctypes.byref(big), None)
+    assert rc == L.ERR_INVALID_ARG
+
+
+def test_missing_required_outputs(lib):
+    rc, need = _size(n=100)
+    prm = L.Params(4, 0, 0, 0, 0, 0)
+    parts = L.Parts(0, 0, 0, 0, 0)
+    big = ctypes.c_size_t(need)
+    rc = lib.lbsort_sort_keys(L.U64, ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), 100, ctypes.byref(prm),
+                              ctypes.byref(parts), ctypes.c_void_p(1 << 30), ctypes.byref(big), None)
+    assert rc == L.ERR_INVALID_ARG
+    rc = lib.lbsort_sort_keys(L.U64, None, None, 100, ctypes.byref(prm), None, ctypes.c_void_p(1 << 30),
+                              ctypes.byref(big), None)
+    assert rc == L.ERR_INVALID_ARG

@@ -1,0 +1,137 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit
+for bit, on every output: sorted keys and values, partition offsets and
+counts, splitters, send counts and the cut matrix.
+
+Sizes span many radix tiles (4096 keys) and merge tiles with ragged tails, and
+the edge cases of the method: empty input, N < P, P = 1, blocks that fit one
+tile, all keys equal, heavy duplication, and every investigator mode.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sample_sort as O
+from paper_1611_00463_amd import datagen
+from paper_1611_00463_amd import lbsort as L
+from tests.parity import check_case, compare, to_dev, to_host, u64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ws():
+    return L.Workspace("cuda")
+
+
+def test_config1_full_size(ws):
+    """1,048,576 uniform u64 keys, P=8, 16 samples per block, keys only."""
+    keys = datagen.uniform_keys(1 << 20, seed=1)
+    check_case(keys, None, 8, 16, ws=ws)
+
+
+@pytest.mark.parametrize("n", [3_000_017, 1 << 21])
+def test_pairs_p64(ws, n):
+    keys = datagen.uniform_keys(n, seed=2)
+    vals = datagen.index_values(n)
+    check_case(keys, vals, 64, 512, ws=ws)
+
+
+@pytest.mark.parametrize("mode", [O.INV_COUNT, O.INV_NONE, O.INV_PAPER])
+def test_duplicate_heavy_modes(ws, mode):
+    n = 2_000_003
+    keys = datagen.duplicate_heavy_keys(n, seed=3)
+    vals = datagen.index_values(n)
+    r, o = check_case(keys, vals, 64, 512, mode=mode, ws=ws)
+    if mode == O.INV_COUNT:
+        assert o.part_counts.max() / (n / 64) <= 1.05
+
+
+def test_u32_pairs(ws):
+    n = 1_234_567
+    keys = datagen.uniform_keys(n, seed=5, dtype=np.uint32)
+    check_case(keys, datagen.index_values(n), 8, 0, ws=ws)
+    keys = datagen.normal_u32(n, seed=6)
+    check_case(keys, datagen.index_values(n), 13, 0, ws=ws)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 100, 4095, 4096, 4097, 8191, 50_000])
+@pytest.mark.parametrize("P", [1, 2, 3, 8, 13])
+def test_small_and_ragged(ws, n, P):
+    keys = datagen.uniform_keys(n, seed=n + 17 * P)
+    keys[::3] = keys[0] if n else keys[::3]          # some duplicates
+    check_case(keys, datagen.index_values(n), P, 4, ws=ws)
+
+
+def test_all_equal_and_sorted_inputs(ws):
+    n = 300_001
+    check_case(np.full(n, 7, dtype=np.uint64), datagen.index_values(n), 16, 8, ws=ws)
+    srt = np.sort(datagen.uniform_keys(n, seed=9))
+    check_case(srt, datagen.index_values(n), 16, 8, ws=ws)
+    check_case(srt[::-1].copy(), datagen.index_values(n), 16, 8, ws=ws)
+    k32 = np.sort(datagen.uniform_keys(n, seed=10, dtype=np.uint32))[::-1].copy()
+    check_case(k32, None, 10, 0, ws=ws)
+
+
+@pytest.mark.parametrize("fanin", [2, 4, 8, 16])
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_tuning_settings_do_not_change_bytes(ws, fanin, tile):
+    n = 700_001
+    keys = datagen.duplicate_heavy_keys(n, seed=11)
+    check_case(keys, datagen.index_values(n), 37, 64, fanin=fanin, tile=tile, ws=ws)
+
+
+def test_local_sort_stage(ws):
+    """Step 1 alone: every block sorted on its own, against the oracle's blocks."""
+    n, P = 1_000_003, 16
+    keys = datagen.uniform_keys(n, seed=12)
+    vals = datagen.index_values(n)
+    seg = to_dev(np.array([0, n], dtype=np.uint64))
+    k, v, buf = L.local_sort(to_dev(keys), seg, P, vals=to_dev(vals))
+    L.check(buf)
+    o = O.sample_sort(keys, vals, P)
+    np.testing.assert_array_equal(to_host(k), np.concatenate(o.sorted_blocks))
+    np.testing.assert_array_equal(to_host(v), np.concatenate(o.sorted_vals))
+
+
+def test_batch_instances(ws):
+    """Several data sets at once; each instance equals its own oracle run."""
+    sizes = [0, 1, 5, 4096, 4097, 10_000, 123_457, 0, 33, 250_000, 3, 65_536]
+    rng = np.random.default_rng(3)
+    parts_k, parts_v = [], []
+    for i, n in enumerate(sizes):
+        if i % 3 == 0:
+            k = datagen.uniform_keys(n, seed=100 + i, dtype=np.uint32)
+        elif i % 3 == 1:
+            k = np.sort(datagen.uniform_keys(n, seed=100 + i, dtype=np.uint32))
+        else:
+            k = rng.integers(0, 5, size=n).astype(np.uint32)
+        parts_k.append(k)
+        parts_v.append(np.arange(n, dtype=np.uint32))
+    keys = np.concatenate(parts_k)
+    vals = np.concatenate(parts_v)
+    seg = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    for P in (1, 8, 5):
+        r = L.sort_batch(to_dev(keys), to_dev(seg), P, vals=to_dev(vals), s=32, want_send=True, want_cuts=True)
+        L.check(r.workspace)
+        for b in range(len(sizes)):
+            a, e = int(seg[b]), int(seg[b + 1])
+            o = O.sample_sort(keys[a:e], vals[a:e], P, 32)
+            compare(r, o, P, b=b, seg=(a, e))
+
+
+def test_repeat_runs_identical(ws):
+    """Same input, same workspace, five runs: identical bytes (races would show)."""
+    n = 2_500_000
+    keys = datagen.duplicate_heavy_keys(n, seed=13)
+    kd = to_dev(keys)
+    vd = to_dev(datagen.index_values(n))
+    first = None
+    for _ in range(5):
+        r = L.sort_pairs(kd, vd, 64, s=512, workspace=ws)
+        L.check(r.workspace)
+        cur = (to_host(r.keys), to_host(r.vals), u64(r.part_offsets))
+        if first is None:
+            first = cur
+        else:
+            for a, b in zip(first, cur):
+                np.testing.assert_array_equal(a, b)
