@@ -166,8 +166,9 @@ int lbsort_load_tuning(const char *cache_path);
  * calls is bracketed by two HIP events recorded on the call's stream.
  * lbsort_profile_read synchronises those events, writes one line per kernel
  * name, "name launches total_ms\n", into buf (host, len bytes, NUL
- * terminated), clears the records and returns the number of bytes needed
- * (excluding the NUL).  Not thread safe; meant for benchmarks.
+ * terminated) and returns the number of bytes needed (excluding the NUL).
+ * With buf != NULL the records are cleared; a size query (buf == NULL)
+ * keeps them.  Not thread safe; meant for benchmarks.
  */
 int lbsort_profile_enable(int on);
 int lbsort_profile_read(char *buf, size_t len);

@@ -17,10 +17,13 @@ design notes of the repository):
 * blocks: block i holds input positions [floor(i N / P), floor((i+1) N / P));
 * step 1 uses a *stable* local sort (the paper's quicksort leaves the order
   of equal keys unspecified);
-* step 2 takes s_i = min(s, n_i) samples at the chunk midpoints
-  floor((2j+1) n_i / (2 s_i)), j = 0..s_i-1;
-* step 3 takes splitter k (k = 1..P-1) at rank max(0, floor(k S / P) - 1) of
-  the pooled samples (S = total sample count);
+* step 2 takes s_i = min(s, n_i) samples at the chunk starts
+  floor(j n_i / s_i), j = 0..s_i-1, the regular sampling of PSRS (Shi and
+  Schaeffer 1992), the sample sort the paper builds on;
+* step 3 takes splitter k (k = 1..P-1) at rank
+  min(S-1, floor(k S / P) + floor(P/2) - 1) of the pooled samples (S = total
+  sample count), PSRS's pivot rank: the middle of the k-th group of P pooled
+  samples, which does not shift the splitters when all blocks look alike;
 * step 4 bounds: partition k takes keys in [v_k, v_{k+1}) before the
   investigator moves cuts inside runs of keys equal to a splitter;
 * the investigator (Section IV.B, Fig. 3c) in three modes:
@@ -70,7 +73,7 @@ def local_sort(keys: np.ndarray, vals: np.ndarray | None, bounds: list[int]):
 def sample_positions(n: int, s: int) -> np.ndarray:
     si = min(s, n)
     j = np.arange(si, dtype=np.int64)
-    return ((2 * j + 1) * n) // (2 * si) if si > 0 else j
+    return (j * n) // si if si > 0 else j
 
 
 def regular_samples(sorted_block: np.ndarray, s: int) -> np.ndarray:
@@ -86,7 +89,7 @@ def select_splitters(samples: list[np.ndarray], P: int, dtype) -> tuple[np.ndarr
     v = np.zeros(max(P - 1, 0), dtype=dtype)
     if S > 0:
         for k in range(1, P):
-            v[k - 1] = pool[max(0, k * S // P - 1)]
+            v[k - 1] = pool[min(S - 1, k * S // P + P // 2 - 1)]
     return v, pool
 
 
@@ -163,6 +166,26 @@ def exchange(cuts: np.ndarray):
     return C, G, D
 
 
+def exchange_receive(sorted_blocks, sorted_vals, cuts: np.ndarray, C: np.ndarray, D: np.ndarray, N: int):
+    """Step 5 itself: every block writes its slice for processor k at the
+    receive offset D[i][k]; all writes land in disjoint places, so they can
+    happen at once (Section IV.C).  Returns the receive buffer(s)."""
+    P = cuts.shape[0]
+    dtype = sorted_blocks[0].dtype if P else np.uint64
+    rk = np.zeros(N, dtype=dtype)
+    rv = None if sorted_vals[0] is None else np.zeros(N, dtype=np.uint32)
+    written = np.zeros(N, dtype=np.int64)
+    for i in range(P):
+        for k in range(P):
+            a, c = int(cuts[i, k]), int(C[i, k])
+            rk[D[i, k]:D[i, k] + c] = sorted_blocks[i][a:a + c]
+            if rv is not None:
+                rv[D[i, k]:D[i, k] + c] = sorted_vals[i][a:a + c]
+            written[D[i, k]:D[i, k] + c] += 1
+    assert np.all(written == 1), "receive offsets must tile the output exactly once"
+    return rk, rv
+
+
 # ---------------------------------------------------------------- step 6
 def handler_schedule(n_runs: int) -> list[list[tuple[int, int]]]:
     """Fig. 2: round r (r = 1, 2, 4, ...) merges run i+r into run i for every
@@ -236,11 +259,12 @@ def sample_sort(keys: np.ndarray, vals: np.ndarray | None, P: int, s: int = 0,
     lo, hi = search(sk, splitters)                                # step 4
     cuts = investigator(lo, hi, sizes, splitters, mode)
     C, G, D = exchange(cuts)                                      # step 5
+    recv_k, recv_v = exchange_receive(sk, sv, cuts, C, D, N)
     out_k = np.empty(N, dtype=dtype)
     out_v = None if vals is None else np.empty(N, dtype=vals.dtype)
     for k in range(P):                                            # step 6
-        rk = [sk[i][cuts[i, k]:cuts[i, k + 1]] for i in range(P)]
-        rv = [None if vals is None else sv[i][cuts[i, k]:cuts[i, k + 1]] for i in range(P)]
+        rk = [recv_k[D[i, k]:D[i, k] + C[i, k]] for i in range(P)]
+        rv = [None if vals is None else recv_v[D[i, k]:D[i, k] + C[i, k]] for i in range(P)]
         mk, mv = handler_merge(rk, rv)
         out_k[G[k]:G[k + 1]] = mk
         if vals is not None:

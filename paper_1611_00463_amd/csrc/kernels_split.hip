@@ -8,8 +8,8 @@
 
 namespace lbs {
 
-// Step 2: s_i = min(s, n_i) samples of sorted block i at the chunk midpoints
-// floor((2j+1) n_i / (2 s_i)).
+// Step 2: s_i = min(s, n_i) regular samples of sorted block i at the chunk
+// starts floor(j n_i / s_i) (the regular sampling of PSRS).
 template <typename K>
 __global__ __launch_bounds__(256) void k_samples(Plan p, const K* __restrict__ sorted, u64 max_samples) {
   const u64 x = (u64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void k_samples(Plan p, const K* __restrict__ s
   const u64 si = p.samp_start[blk + 1] - p.samp_start[blk];
   const u64 bs = p.blk_start[blk];
   const u64 n = p.blk_start[blk + 1] - bs;
-  const u64 pos = (u64)(((unsigned __int128)(2 * j + 1) * n) / (2 * si));
+  const u64 pos = (u64)(((unsigned __int128)j * n) / si);
   ((K*)p.samples)[x] = sorted[bs + pos];
 }
 
@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256) void k_sample_rank(Plan p, u64 max_samples) {
   if (live && sub == 0) ((K*)p.pool)[dst + cnt] = key;
 }
 
-// Step 3, part 2: splitter k = pool[max(0, floor(k S / P) - 1)].
+// Step 3, part 2: splitter k = pool[min(S-1, floor(k S / P) + floor(P/2) - 1)],
+// the middle of the k-th group of P pooled samples (PSRS's pivot rank).
 template <typename K>
 __global__ __launch_bounds__(256) void k_splitters(Plan p) {
   const u32 x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -62,8 +63,8 @@ __global__ __launch_bounds__(256) void k_splitters(Plan p) {
   const u64 a = p.samp_start[b * p.P], S = p.samp_start[(b + 1) * p.P] - a;
   K v = 0;
   if (S > 0) {
-    const u64 r = ((u64)k * S) / p.P;
-    v = ((const K*)p.pool)[a + (r > 0 ? r - 1 : 0)];
+    const u64 r = ((u64)k * S) / p.P + p.P / 2 - 1;
+    v = ((const K*)p.pool)[a + (r < S - 1 ? r : S - 1)];
   }
   ((K*)p.splitters)[x] = v;
 }
@@ -82,14 +83,14 @@ __global__ __launch_bounds__(256) void k_search(Plan p, const K* __restrict__ so
   const u32 b = blk / p.P;
   const K v = ((const K*)p.splitters)[b * per + k];
   const u64 bs = p.blk_start[blk], n = p.blk_start[blk + 1] - bs;
-  // window from the samples: sample j sits at floor((2j+1) n / (2 si))
+  // window from the samples: sample j sits at floor(j n / si)
   const u64 sa = p.samp_start[blk], si = p.samp_start[blk + 1] - sa;
   const K* smp = (const K*)p.samples;
   u64 wlo = 0, whi = n;
   if (si > 0) {
     const u64 j = upper ? bsearch_count<K, true>(smp, sa, sa + si, v) - sa : bsearch_count<K, false>(smp, sa, sa + si, v) - sa;
-    if (j > 0) wlo = (u64)(((unsigned __int128)(2 * (j - 1) + 1) * n) / (2 * si)) + 1;
-    if (j < si) whi = (u64)(((unsigned __int128)(2 * j + 1) * n) / (2 * si));
+    if (j > 0) wlo = (u64)(((unsigned __int128)(j - 1) * n) / si) + 1;
+    if (j < si) whi = (u64)(((unsigned __int128)j * n) / si);
   }
   const u64 r = upper ? bsearch_count<K, true>(sorted + bs, wlo, whi, v) : bsearch_count<K, false>(sorted + bs, wlo, whi, v);
   (upper ? p.hi : p.lo)[(u64)blk * per + k] = r;

@@ -305,6 +305,7 @@ extern "C" int lbsort_profile_enable(int on) {
 
 extern "C" int lbsort_profile_read(char* buf, size_t len) {
   using namespace lbs;
+  // A size query (buf == NULL) leaves the records in place.
   std::vector<std::string> names;
   std::vector<double> ms;
   std::vector<int> cnt;
@@ -322,8 +323,6 @@ extern "C" int lbsort_profile_read(char* buf, size_t len) {
     ms[i] += t;
     cnt[i] += 1;
   }
-  g_recs.clear();
-  g_next_event = 0;
   std::string out;
   char line[256];
   for (size_t i = 0; i < names.size(); ++i) {
@@ -334,6 +333,8 @@ extern "C" int lbsort_profile_read(char* buf, size_t len) {
     size_t n = out.size() < len - 1 ? out.size() : len - 1;
     memcpy(buf, out.data(), n);
     buf[n] = 0;
+    g_recs.clear();
+    g_next_event = 0;
   }
   return (int)out.size();
 }

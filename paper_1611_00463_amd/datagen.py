@@ -186,3 +186,42 @@ def serve_pool_u64(dist: int, n: int, seed: int = 5) -> np.ndarray:
         return u64(s + 7, r)
     k = np.sort(uniform_keys(n, s))
     return k if dist == 2 else k[::-1].copy()
+
+
+# --------------------------------------------------------------------------
+# The same streams generated on the device with torch int64 arithmetic
+# (wrapping multiply, logical shifts by masking); bit-identical to u64().
+# --------------------------------------------------------------------------
+
+def _i64(c: int) -> int:
+    c &= 0xFFFFFFFFFFFFFFFF
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def _lsr(z, s: int):
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def u64_torch(seed: int, start: int, count: int, device="cuda"):
+    import torch
+    i = torch.arange(start, start + count, dtype=torch.int64, device=device)
+    z = (i + 1) * _i64(0x9E3779B97F4A7C15) + _i64(seed)
+    z = (z ^ _lsr(z, 30)) * _i64(0xBF58476D1CE4E5B9)
+    z = (z ^ _lsr(z, 27)) * _i64(0x94D049BB133111EB)
+    z = z ^ _lsr(z, 31)
+    return z.view(torch.uint64)
+
+
+def uniform_keys_torch(n: int, seed: int, device="cuda", chunk: int = 1 << 26):
+    """uniform_keys(n, seed) as a device tensor, generated in chunks."""
+    import torch
+    out = torch.empty(n, dtype=torch.uint64, device=device)
+    for a in range(0, n, chunk):
+        e = min(n, a + chunk)
+        out[a:e] = u64_torch(seed, a, e - a, device)
+    return out
+
+
+def index_values_torch(n: int, device="cuda"):
+    import torch
+    return torch.arange(n, dtype=torch.int64, device=device).to(torch.int32).view(torch.uint32)

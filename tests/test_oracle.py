@@ -130,8 +130,9 @@ def test_none_mode_cuts_are_lower_bounds():
 
 
 def test_every_element_sampled_gives_exact_quantiles():
-    """With s >= block size every element is a sample, so splitter k is the
-    element of rank max(0, floor(kN/P)-1) of the whole input."""
+    """With s >= block size every element is a sample, so the pool is the whole
+    input in order and splitter k is its element of rank
+    min(N-1, floor(kN/P) + floor(P/2) - 1)."""
     rng = np.random.default_rng(9)
     for _ in range(100):
         n = int(rng.integers(1, 80))
@@ -139,17 +140,23 @@ def test_every_element_sampled_gives_exact_quantiles():
         keys = rand_keys(rng, n)
         r = O.sample_sort(keys, None, P, n + 1)
         srt = sorted(int(x) for x in keys)
+        assert sorted(int(x) for x in np.concatenate(r.samples)) == srt
         for k in range(1, P):
-            assert int(r.splitters[k - 1]) == srt[max(0, k * n // P - 1)]
+            assert int(r.splitters[k - 1]) == srt[min(n - 1, k * n // P + P // 2 - 1)]
 
 
-def test_single_sample_is_block_median():
+def test_samples_are_block_order_statistics():
+    """Sample j of a block of n keys is its element of rank floor(j n / s):
+    with s = 1 the block minimum, with s = 2 the minimum and the element of
+    rank floor(n/2)."""
     rng = np.random.default_rng(10)
     for _ in range(50):
         n = int(rng.integers(1, 50))
         keys = rand_keys(rng, n)
-        r = O.sample_sort(keys, None, 1, 1)
-        assert int(r.samples[0][0]) == sorted(int(x) for x in keys)[n // 2]
+        srt = sorted(int(x) for x in keys)
+        assert [int(x) for x in O.sample_sort(keys, None, 1, 1).samples[0]] == [srt[0]]
+        two = [int(x) for x in O.sample_sort(keys, None, 1, 2).samples[0]]
+        assert two == ([srt[0], srt[n // 2]] if n >= 2 else [srt[0]])
 
 
 def test_partition_key_ranges_are_monotone():
@@ -207,6 +214,8 @@ def test_worked_example():
         assert r.cuts.tolist() == exp["cuts"]
         assert r.part_counts.tolist() == exp["part_counts"]
         assert r.part_offsets.tolist() == exp["part_offsets"]
+        if "recv_offsets" in exp:
+            assert r.recv_offsets.tolist() == exp["recv_offsets"]
         assert r.vals.tolist() == exp["vals_out"]
 
 
@@ -260,8 +269,9 @@ def test_merge_two_against_python_sorted():
 
 # ------------------------------------------------------------------ balance
 def test_balance_guarantee_adversarial():
-    """COUNT: |G_k - kN/P| <= N/(2s) + P + 1 for any input, so every partition
-    holds at most N/P + N/s + 2P + 3 keys (blocks of at least s keys)."""
+    """COUNT: |G_k - kN/P| <= (n/s) ceil(P/2) + P + 1 for any input (n = block
+    size, blocks of at least s keys, s >= P/2), so every partition holds at
+    most N/P + (N/s)(1 + 1/P) + 2P + 3 keys."""
     rng = np.random.default_rng(13)
     gens = [
         lambda n: np.full(n, 42, dtype=np.uint64),
@@ -275,7 +285,7 @@ def test_balance_guarantee_adversarial():
         for P, s, n in [(8, 16, 20000), (16, 8, 30000), (5, 3, 9000), (64, 32, 65536)]:
             keys = g(n)
             r = O.sample_sort(keys, None, P, s, O.INV_COUNT)
-            assert int(r.part_counts.max()) <= n / P + n / s + 2 * P + 3
+            assert int(r.part_counts.max()) <= n / P + (n / s) * (1 + 1 / P) + 2 * P + 3
             assert np.all(np.diff(r.keys.astype(object)) >= 0)
 
 
