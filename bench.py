@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--fanin", type=int, default=0)
     ap.add_argument("--merge-tile", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU exchange is not "
@@ -111,6 +113,15 @@ def main():
     import numpy as np
     import torch
     from paper_1611_00463_amd import lbsort as L
+
+    if args.copy_calibration:
+        a = torch.ones(args.copy_calibration // 8, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": a.numel() * 8}))
+        return
 
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")

@@ -242,6 +242,26 @@ class SortResult:
     recv_offsets: np.ndarray | None = None
 
 
+def partition_plan(keys: np.ndarray, P: int, s: int = 0, mode: int = INV_COUNT) -> dict:
+    """Steps 1-5 without moving any data: sorted blocks (keys only), samples,
+    splitters, searches, cuts and the range table.  Used where the whole
+    merge would take too long on the CPU."""
+    keys = np.asarray(keys)
+    N = len(keys)
+    if s <= 0:
+        s = default_sample_count(P, keys.dtype.itemsize)
+    bounds = block_bounds(N, P)
+    sizes = [bounds[i + 1] - bounds[i] for i in range(P)]
+    sk, _ = local_sort(keys, None, bounds)
+    samples = [regular_samples(b, s) for b in sk]
+    splitters, _ = select_splitters(samples, P, keys.dtype)
+    lo, hi = search(sk, splitters)
+    cuts = investigator(lo, hi, sizes, splitters, mode)
+    C, G, D = exchange(cuts)
+    return dict(samples=samples, splitters=splitters, lo=lo, hi=hi, cuts=cuts, send_counts=C,
+                part_offsets=G, part_counts=np.diff(G), recv_offsets=D)
+
+
 def sample_sort(keys: np.ndarray, vals: np.ndarray | None, P: int, s: int = 0,
                 mode: int = INV_COUNT) -> SortResult:
     """The whole method on one array: steps 1 to 6 of Section IV."""

@@ -58,13 +58,13 @@ struct Shape {
   bool has_small, has_large;
   u64 max_tiles, max_samples;
   u32 ng0;          // merge groups of pass 0 (the largest pass)
-  u64 mslots;
+  u64 mtiles;       // merge tiles of one pass, worst case
   bool local_only;  // step 1 only
 };
 
 struct Layout {
-  u64 counters, blk_start, tstart, small_list, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
-      splitters, mtile, mcut, tmpk, tmpv, seg, total;
+  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
+      splitters, mtile, rec_start, rec_end, rec_out, rec_n, slot_grp, grp_run, grp_out, tmpk, tmpv, seg, total;
 };
 
 static Layout make_layout(const Shape& sh) {
@@ -81,6 +81,8 @@ static Layout make_layout(const Shape& sh) {
   l.blk_start = take((NB + 1) * 8);
   l.tstart = take((NB + 1) * 4);
   l.small_list = take(NB * 4);
+  l.large_list = take(NB * 4);
+  l.rem_prefix = take((NB + 1) * 4);
   l.samp_start = take((NB + 1) * 8);
   l.hist = take(NB * sh.D * RADIX * 4);
   l.status = take(sh.max_tiles * RADIX * 8);
@@ -93,7 +95,13 @@ static Layout make_layout(const Shape& sh) {
   l.G = take(B * (P + 1) * 8);
   l.splitters = take(B * (P - 1) * K);
   l.mtile = take(((u64)sh.ng0 + 1) * 4);
-  l.mcut = take(sh.mslots * sh.F * 8);
+  l.rec_start = take(sh.mtiles * sh.F * 8);
+  l.rec_end = take(sh.mtiles * sh.F * 8);
+  l.rec_out = take(sh.mtiles * 8);
+  l.rec_n = take(sh.mtiles * 4);
+  l.slot_grp = take((sh.mtiles + sh.ng0 + 1) * 4);
+  l.grp_run = take((u64)sh.ng0 * sh.F * 16);
+  l.grp_out = take((u64)sh.ng0 * 16);
   const u64 stages = (u64)sh.D + sh.L;
   const bool need_tmp = stages > 1;
   l.tmpk = take(need_tmp ? sh.total_n * K : 0);
@@ -171,7 +179,7 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   if (sh.max_tiles >= (1ull << 31)) return fail(LBSORT_ERR_UNSUPPORTED, "too many radix tiles");
   const u64 Q0 = (p.P + F - 1) / F;
   sh.ng0 = (u32)(NB * Q0);
-  sh.mslots = sh.L ? total_n / sh.TM + 2ull * sh.ng0 + 1 : 0;
+  sh.mtiles = sh.L ? total_n / sh.TM + sh.ng0 + 1 : 0;
   return LBSORT_OK;
 }
 
@@ -194,6 +202,8 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.blk_start = (u64*)(ws + lay.blk_start);
   p.tstart = (u32*)(ws + lay.tstart);
   p.small_list = (u32*)(ws + lay.small_list);
+  p.large_list = (u32*)(ws + lay.large_list);
+  p.rem_prefix = (u32*)(ws + lay.rem_prefix);
   p.counters = (u32*)(ws + lay.counters);
   p.hist = (u32*)(ws + lay.hist);
   p.status = (u64*)(ws + lay.status);
@@ -207,9 +217,15 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.G = (u64*)(ws + lay.G);
   p.splitters = ws + lay.splitters;
   p.mtile = (u32*)(ws + lay.mtile);
-  p.mcut = (u64*)(ws + lay.mcut);
+  p.rec_start = (u64*)(ws + lay.rec_start);
+  p.rec_end = (u64*)(ws + lay.rec_end);
+  p.rec_out = (u64*)(ws + lay.rec_out);
+  p.rec_n = (u32*)(ws + lay.rec_n);
+  p.slot_grp = (u32*)(ws + lay.slot_grp);
+  p.grp_run = (u64*)(ws + lay.grp_run);
+  p.grp_out = (u64*)(ws + lay.grp_out);
   p.ng_max = sh.ng0;
-  p.mslots_max = (u32)sh.mslots;
+  p.mtiles_max = (u32)sh.mtiles;
   if (seg_in) {
     p.seg = seg_in;
   } else {

@@ -96,6 +96,25 @@ __global__ __launch_bounds__(1024) void k_merge_plan(Plan p, Level L) {
     __syncthreads();
   }
   if (tid == 0) p.mtile[L.NG] = (u32)carry;
+  // Group descriptors, and the owner group of every boundary slot, so that a
+  // boundary's wave starts with independent loads only.
+  for (u32 g = tid; g < L.NG; g += 1024) {
+    u64 off, len;
+    group_info(p, L, g, off, len);
+    p.grp_out[2 * (u64)g] = off;
+    p.grp_out[2 * (u64)g + 1] = len;
+    for (u32 r = 0; r < p.F; ++r) {
+      u64 ro, rl;
+      run_info(p, L, g, r, ro, rl);
+      p.grp_run[((u64)g * p.F + r) * 2] = ro;
+      p.grp_run[((u64)g * p.F + r) * 2 + 1] = rl;
+    }
+  }
+  __syncthreads();
+  for (u32 g = tid; g < L.NG; g += 1024) {
+    const u32 a = p.mtile[g] + g, e = p.mtile[g + 1] + g + 1;
+    for (u32 q = a; q < e; ++q) p.slot_grp[q] = g;
+  }
 }
 
 // ----------------------------------------------------------------- selection
@@ -109,19 +128,29 @@ __global__ __launch_bounds__(1024) void k_merge_plan(Plan p, Level L) {
 // Every round strictly shrinks every non-empty window, so the loop ends with
 // lo = hi = the split.
 template <typename K, int F, int M>
-__device__ inline u64 wave_select(const K* __restrict__ src, u64 roff, u64 rlen, u64 total, u64 a,
-                                  u32* counters) {
+__device__ inline u64 wave_select(const K* __restrict__ src, u64 roff, u64 lo, u64 hi, u64 a, u32* counters) {
   constexpr int NPIV = 64 * M / F;
   constexpr int QPR = NPIV / F;
   static_assert(QPR >= 1, "every run needs a pivot per round");
   const u32 lane = threadIdx.x & 63;
   const u32 r = lane % F;
-  u64 lo = a + rlen > total ? a + rlen - total : 0;
-  u64 hi = a < rlen ? a : rlen;
   for (int round = 0; round < 96; ++round) {
-    if (__ballot(lo < hi) == 0) return lo;
-    u64 nlo = lo, nhi = hi;
-    u64 pos[M], slo[M], shi[M];
+    // widest window of the wave: every lane runs the same number of steps
+    u64 wmax = hi - lo, wsum = hi - lo, lsum = lo;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const u64 y = __shfl_xor(wmax, o);
+      wmax = y > wmax ? y : wmax;
+    }
+    if (wmax == 0) return lo;
+#pragma unroll
+    for (int o = 1; o < F; o <<= 1) {
+      wsum += __shfl_xor(wsum, o);
+      lsum += __shfl_xor(lsum, o);
+    }
+    // The first round puts the pivots around the proportional guess
+    // lo + (a - sum lo) W / sum W; later rounds spread them evenly.
+    u64 pos[M], base[M];
     K px[M];
     bool pvalid[M];
     u32 own[M];
@@ -136,29 +165,41 @@ __device__ inline u64 wave_select(const K* __restrict__ src, u64 roff, u64 rlen,
       const u64 off_o = __shfl(roff, (int)own[m]);
       const u64 W = hi_o - lo_o;
       pvalid[m] = W > 0;
-      pos[m] = lo_o + (W * (qi + 1)) / (QPR + 1);
+      u64 at = lo_o + (W * (qi + 1)) / (QPR + 1);
+      if (round == 0 && wsum > 0) {
+        const u64 guess = lo_o + (u64)(((unsigned __int128)(a - lsum) * W) / wsum);
+        const u64 d = W / 64 > 1 ? W / 64 : 1;
+        const int k = (int)qi - QPR / 2;  // -QPR/2 .. QPR/2-1
+        const u64 mag = d << (2 * (k < 0 ? -k - 1 : k));
+        u64 want = k < 0 ? (guess > mag ? guess - mag : 0) : guess + mag - (k == 0 ? d : 0);
+        at = want < lo_o ? lo_o : (want >= hi_o ? (hi_o > 0 ? hi_o - 1 : 0) : want);
+      }
+      pos[m] = at;
       px[m] = pvalid[m] ? src[off_o + pos[m]] : (K)0;
-      slo[m] = lo;
-      shi[m] = hi;
+      base[m] = lo;
     }
-    // M interleaved binary searches in this lane's run window
-    bool any = true;
-    while (any) {
-      any = false;
+    // M interleaved searches over this lane's run window [lo, hi), power-of-two
+    // steps: base ends at lo + #elements of the window that precede the pivot.
+    u64 step = 1;
+    while (step * 2 <= wmax) step *= 2;
+    for (; step > 0; step >>= 1) {
+      K v[M];
 #pragma unroll
       for (int m = 0; m < M; ++m) {
-        if (slo[m] < shi[m] && own[m] != r) {
-          const u64 mid = slo[m] + ((shi[m] - slo[m]) >> 1);
-          const K v = src[roff + mid];
-          const bool right = (r < own[m]) ? (v <= px[m]) : (v < px[m]);
-          if (right) slo[m] = mid + 1; else shi[m] = mid;
-          any = true;
-        }
+        const bool ok = base[m] + step <= hi;
+        v[m] = ok ? src[roff + base[m] + step - 1] : (K)0;
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const bool ok = base[m] + step <= hi;
+        const bool before = (r < own[m]) ? (v[m] <= px[m]) : (v[m] < px[m]);
+        if (ok && before) base[m] += step;
       }
     }
+    u64 nlo = lo, nhi = hi;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const u64 c = (own[m] == r) ? pos[m] : slo[m];
+      const u64 c = (own[m] == r) ? pos[m] : base[m];
       u64 tot = c;
 #pragma unroll
       for (int o = 1; o < F; o <<= 1) tot += __shfl_xor(tot, o);
@@ -167,8 +208,7 @@ __device__ inline u64 wave_select(const K* __restrict__ src, u64 roff, u64 rlen,
           const u64 cand = (own[m] == r) ? pos[m] + 1 : c;
           nlo = cand > nlo ? cand : nlo;
         } else {
-          const u64 cand = c;
-          nhi = cand < nhi ? cand : nhi;
+          nhi = c < nhi ? c : nhi;
         }
       }
     }
@@ -185,34 +225,63 @@ __device__ inline u64 wave_select(const K* __restrict__ src, u64 roff, u64 rlen,
   return lo;
 }
 
-template <typename K, int F, int M>
+// One wave per tile boundary.  Group g owns boundary slots
+// [mtile[g] + g, mtile[g+1] + g + 1): boundary t of the group starts tile
+// mtile[g] + t and ends tile mtile[g] + t - 1.  The wave writes those tiles'
+// records (absolute source offsets of every run, output offset, count), so a
+// merge tile reads everything it needs with independent loads.
+// Two phases: COARSE handles every COARSE_EVERY-th boundary (and the last)
+// from the whole runs; FINE handles the others, starting from the windows
+// between the cuts of the two coarse boundaries around them (the split of
+// the first a elements only moves forward as a grows).
+constexpr u32 COARSE_EVERY = 16;
+
+template <typename K, int F, int M, bool FINE>
 __global__ __launch_bounds__(256) void k_partition(Plan p, Level L, const K* __restrict__ src) {
   const u32 q = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const u32 lane = threadIdx.x & 63;
   const u32 total_tiles = p.mtile[L.NG];
   if (q >= total_tiles + L.NG) return;
-  // group g owns boundary slots [mtile[g] + g, mtile[g+1] + g + 1)
-  u32 lo = 0, hi = L.NG;
-  while (hi - lo > 1) {
-    const u32 mid = (lo + hi) >> 1;
-    if (p.mtile[mid] + mid <= q) lo = mid; else hi = mid;
-  }
-  const u32 g = lo;
-  const u32 t = q - (p.mtile[g] + g);
-  const u32 nt = p.mtile[g + 1] - p.mtile[g];
-  if (t > nt) return;
-  u64 goff, glen;
-  group_info(p, L, g, goff, glen);
-  u64 roff = 0, rlen = 0;
-  if (lane < (u32)F) run_info(p, L, g, lane, roff, rlen);
-  roff = __shfl(roff, (int)(lane % F));
-  rlen = __shfl(rlen, (int)(lane % F));
+  const u32 g = p.slot_grp[q];
+  const u32 t0 = p.mtile[g];
+  const u32 t = q - (t0 + g);
+  const u32 nt = p.mtile[g + 1] - t0;
+  if (t > nt || nt == 0) return;
+  const bool coarse = (t % COARSE_EVERY) == 0 || t == nt;
+  if (coarse == FINE) return;
+  const u64 goff = p.grp_out[2 * (u64)g], glen = p.grp_out[2 * (u64)g + 1];
+  const u64 roff = p.grp_run[((u64)g * F + lane % F) * 2];
+  const u64 rlen = p.grp_run[((u64)g * F + lane % F) * 2 + 1];
   const u64 a = (u64)t * p.TM < glen ? (u64)t * p.TM : glen;
   u64 cut;
-  if (a == 0) cut = 0;
-  else if (a == glen) cut = rlen;
-  else cut = wave_select<K, F, M>(src, roff, rlen, glen, a, p.counters);
-  if (lane < (u32)F) p.mcut[(u64)q * F + lane] = cut;
+  if (a == 0) {
+    cut = 0;
+  } else if (a == glen) {
+    cut = rlen;
+  } else {
+    u64 lo, hi;
+    if (FINE) {
+      const u32 tl = t - t % COARSE_EVERY;
+      const u32 tr = tl + COARSE_EVERY < nt ? tl + COARSE_EVERY : nt;
+      lo = p.rec_start[(u64)(t0 + tl) * F + lane % F] - roff;
+      hi = p.rec_end[(u64)(t0 + tr - 1) * F + lane % F] - roff;
+      if (hi > rlen) hi = rlen;
+      if (lo > hi) lo = hi;
+    } else {
+      lo = a + rlen > glen ? a + rlen - glen : 0;
+      hi = a < rlen ? a : rlen;
+    }
+    cut = wave_select<K, F, M>(src, roff, lo, hi, a, p.counters);
+  }
+  if (lane < (u32)F) {
+    if (t < nt) p.rec_start[(u64)(t0 + t) * F + lane] = roff + cut;
+    if (t > 0) p.rec_end[(u64)(t0 + t - 1) * F + lane] = roff + cut;
+  }
+  if (lane == 0 && t < nt) {
+    p.rec_out[t0 + t] = goff + a;
+    const u64 left = glen - a;
+    p.rec_n[t0 + t] = (u32)(left < (u64)p.TM ? left : (u64)p.TM);
+  }
 }
 
 // ----------------------------------------------------------------- merge tile
@@ -226,35 +295,29 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
   __shared__ u32 s_v[HASV ? TM : 1];
   __shared__ u64 s_roff[F];
   __shared__ u32 s_so[F + 1];
-  __shared__ u64 s_out;
   const u32 tid = threadIdx.x;
   const u32 tile = blockIdx.x;
   if (tile >= p.mtile[L.NG]) return;
-  if (tid == 0) {
-    const u32 g = find_seg(p.mtile, L.NG, tile);
-    const u32 t = tile - p.mtile[g];
-    const u64 q0 = (u64)p.mtile[g] + g + t;
-    u64 goff, glen;
-    group_info(p, L, g, goff, glen);
-    // Cuts are clamped into their runs and the tile into its group so that a
-    // wrong split could never address memory outside the buffers.
-    u64 acc = 0;
-    for (int r = 0; r < F; ++r) {
-      u64 off, len;
-      run_info(p, L, g, r, off, len);
-      u64 c0 = p.mcut[q0 * F + r], c1 = p.mcut[(q0 + 1) * F + r];
-      c0 = c0 < len ? c0 : len;
-      c1 = c1 < c0 ? c0 : (c1 < len ? c1 : len);
-      s_roff[r] = off + c0;
-      s_so[r] = (u32)(acc < (u64)TM ? acc : (u64)TM);
-      acc += c1 - c0;
-    }
-    const u64 room = glen - (u64)t * TM;
-    s_so[F] = (u32)(acc < room ? (acc < (u64)TM ? acc : (u64)TM) : (room < (u64)TM ? room : (u64)TM));
-    s_out = goff + (u64)t * TM;
+  // Segment r of this tile is source elements [rec_start[r], rec_end[r]); the
+  // lengths are clamped so that a wrong record could never address memory
+  // outside the tile's LDS or the run.
+  if (tid < (u32)F) {
+    const u64 a = p.rec_start[(u64)tile * F + tid], e = p.rec_end[(u64)tile * F + tid];
+    s_roff[tid] = a;
+    s_so[tid + 1] = (u32)(e > a ? (e - a < (u64)TM ? e - a : (u64)TM) : 0);
   }
   __syncthreads();
-  const u32 n = s_so[F] < (u32)TM ? s_so[F] : (u32)TM;
+  if (tid == 0) {
+    u32 acc = 0;
+    const u32 cap = p.rec_n[tile] < (u32)TM ? p.rec_n[tile] : (u32)TM;
+    s_so[0] = 0;
+    for (int r = 1; r <= F; ++r) {
+      acc += s_so[r];
+      s_so[r] = acc < cap ? acc : cap;
+    }
+  }
+  __syncthreads();
+  const u32 n = s_so[F];
   for (u32 q = tid; q < n; q += NT) {
     u32 r = 0;
 #pragma unroll
@@ -307,7 +370,7 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
     __syncthreads();
     cur ^= 1;
   }
-  const u64 out = s_out;
+  const u64 out = p.rec_out[tile];
   for (u32 q = tid; q < n; q += NT) {
     dst[out + q] = s_k[cur][q];
     if (HASV) dstv[out + q] = s_v[s_i[cur][q]];
@@ -318,10 +381,11 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
 template <typename K, bool HASV, int F, int TM>
 static void run_level(const Plan& p, const Level& L, const K* src, const u32* srcv, K* dst, u32* dstv,
                       u64 max_tiles, hipStream_t s) {
-  constexpr int M = F <= 4 ? 1 : (F == 8 ? 2 : 4);
+  constexpr int M = F == 2 ? 1 : (F == 4 ? 2 : (F == 8 ? 4 : 8));
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_merge_plan, dim3(1), dim3(1024), 0, s, p, L); prof_end(pe_, "merge_plan", s); }
   const u64 slots = max_tiles + L.NG + 1;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition", s); }
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M, false>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition_coarse", s); }
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M, true>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition_fine", s); }
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_merge<K, HASV, F, TM>), dim3((u32)max_tiles), dim3(256), 0, s, p, L, src, srcv, dst,
                      dstv); prof_end(pe_, "merge", s); }
 }

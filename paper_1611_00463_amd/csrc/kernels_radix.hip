@@ -54,15 +54,19 @@ __device__ inline u64 block_exclusive_scan(u64 v, u64* s_w, u64& total) {
 __global__ __launch_bounds__(1024) void k_plan(Plan p) {
   __shared__ u64 s_w[16];
   __shared__ u32 s_bad;
+  __shared__ u32 s_rmin;
   const u32 tid = threadIdx.x;
-  if (tid == 0) s_bad = (p.seg[0] != 0 || p.seg[p.B] != p.total_n) ? 1u : 0u;
+  if (tid == 0) {
+    s_bad = (p.seg[0] != 0 || p.seg[p.B] != p.total_n) ? 1u : 0u;
+    s_rmin = 0xFFFFFFFFu;
+  }
   __syncthreads();
   for (u32 b = tid; b < p.B; b += 1024)
     if (p.seg[b + 1] < p.seg[b]) s_bad = 1u;
   __syncthreads();
   const bool bad = s_bad != 0;
   if (bad && tid == 0) set_error(p.counters, E_SEG);
-  u64 carry_t = 0, carry_s = 0, carry_m = 0;
+  u64 carry_t = 0, carry_s = 0, carry_m = 0, carry_l = 0;
   for (u32 base = 0; base < p.NB; base += 1024) {
     const u32 idx = base + tid;
     u64 n = 0, bs = 0;
@@ -85,6 +89,10 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
     u64 ex = block_exclusive_scan<1024>(tiles, s_w, tot);
     if (idx < p.NB) p.tstart[idx] = (u32)(carry_t + ex);
     carry_t += tot;
+    if (tiles) atomicMin(&s_rmin, (u32)tiles);
+    ex = block_exclusive_scan<1024>(tiles ? 1 : 0, s_w, tot);
+    if (tiles) p.large_list[carry_l + ex] = idx;
+    carry_l += tot;
     ex = block_exclusive_scan<1024>(smp, s_w, tot);
     if (idx < p.NB) p.samp_start[idx] = carry_s + ex;
     carry_s += tot;
@@ -92,11 +100,30 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
     if (small) p.small_list[carry_m + ex] = idx;
     carry_m += tot;
   }
+  if (tid == 0) p.tstart[p.NB] = (u32)carry_t;
+  __syncthreads();
+  const u32 rmin = carry_l ? s_rmin : 0;
+  // prefix over large blocks of the tiles beyond the interleaved head
+  u64 carry_r = 0;
+  for (u32 base = 0; base < (u32)carry_l; base += 1024) {
+    const u32 j = base + tid;
+    u64 extra = 0;
+    if (j < (u32)carry_l) {
+      const u32 blk = p.large_list[j];
+      extra = (u64)(p.tstart[blk + 1] - p.tstart[blk]) - rmin;
+    }
+    u64 tot;
+    const u64 ex = block_exclusive_scan<1024>(extra, s_w, tot);
+    if (j < (u32)carry_l) p.rem_prefix[j] = (u32)(carry_r + ex);
+    carry_r += tot;
+  }
   if (tid == 0) {
-    p.tstart[p.NB] = (u32)carry_t;
+    p.rem_prefix[carry_l] = (u32)carry_r;
     p.samp_start[p.NB] = carry_s;
     p.blk_start[p.NB] = bad ? 0 : p.seg[p.B];
     p.counters[C_NSMALL] = (u32)carry_m;
+    p.counters[C_NLARGE] = (u32)carry_l;
+    p.counters[C_RMIN] = rmin;
   }
 }
 
@@ -218,23 +245,30 @@ __global__ __launch_bounds__(SORT_NT) void k_onesweep(Plan p, const K* __restric
   __shared__ u64 s_gbase[RADIX];
   __shared__ u32 s_lstart[RADIX];
   __shared__ u64 s_scan[NWV];
-  __shared__ K s_keys[SORT_TILE];
-  __shared__ u32 s_vals[HASV ? SORT_TILE : 1];
-  __shared__ u32 s_info[2];
+  // Keys are staged in s_stage; values reuse the same buffer afterwards, and
+  // s_dig keeps each staged position's digit for the value write.
+  __shared__ K s_stage[SORT_TILE];
+  __shared__ uint8_t s_dig[HASV ? SORT_TILE : 1];
+  __shared__ u32 s_info[3];
   const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const u32 shift = pass * RADIX_BITS;
   const u32 total = p.tstart[p.NB];
+  const TileOrder ord{p.counters[C_NLARGE], p.counters[C_RMIN], p.large_list, p.rem_prefix};
   if (tid == 0) {
     const u32 t = atomicAdd(&p.counters[C_TILE0 + pass], 1u);
     s_info[0] = t;
-    s_info[1] = t < total ? find_seg(p.tstart, p.NB, t) : 0u;
+    u32 j = 0, lt = 0;
+    if (t < total) ord.locate(t, j, lt);
+    s_info[1] = j;
+    s_info[2] = lt;
   }
   for (int i = tid; i < NWV * RADIX; i += SORT_NT) (&s_wc[0][0])[i] = 0;
   __syncthreads();
   const u32 t = s_info[0];
   if (t >= total) return;
-  const u32 blk = s_info[1];
-  const u32 lt = t - p.tstart[blk];
+  const u32 jl = s_info[1];
+  const u32 lt = s_info[2];
+  const u32 blk = p.large_list[jl];
   const u64 bstart = p.blk_start[blk];
   const u64 tbase = bstart + (u64)lt * SORT_TILE;
   const u64 rem = p.blk_start[blk + 1] - tbase;
@@ -274,9 +308,9 @@ __global__ __launch_bounds__(SORT_NT) void k_onesweep(Plan p, const K* __restric
     st_release_agent(st, st_pack(epoch, ST_INC, tot));
   } else {
     st_release_agent(st, st_pack(epoch, ST_AGG, tot));
-    u32 pt = t - 1, spins = 0;
+    u32 plt = lt - 1, spins = 0;
     while (true) {
-      const u64 v = ld_acquire_agent(p.status + (u64)pt * RADIX + tid);
+      const u64 v = ld_acquire_agent(p.status + (u64)ord.id_of(jl, plt) * RADIX + tid);
       if ((u32)(v >> 56) != epoch) {
         if (++spins > SPIN_LIMIT) {
           set_error(p.counters, E_SPIN);
@@ -286,8 +320,8 @@ __global__ __launch_bounds__(SORT_NT) void k_onesweep(Plan p, const K* __restric
         continue;
       }
       excl += v & ST_VALMASK;
-      if (((v >> 54) & 3u) == ST_INC) break;
-      --pt;
+      if (((v >> 54) & 3u) == ST_INC || plt == 0) break;
+      --plt;
     }
     st_release_agent(st, st_pack(epoch, ST_INC, excl + tot));
   }
@@ -296,20 +330,27 @@ __global__ __launch_bounds__(SORT_NT) void k_onesweep(Plan p, const K* __restric
   s_lstart[tid] = lstart;
   s_gbase[tid] = bstart + p.hist[((u64)blk * p.D + pass) * RADIX + tid] + excl - lstart;
   __syncthreads();
+  u32 pos[SORT_ITEMS];
 #pragma unroll
   for (int j = 0; j < SORT_ITEMS; ++j) {
-    if (wbase + j * 64 + lane < tile_n) {
-      const u32 pos = s_lstart[dig[j]] + s_wc[w][dig[j]] + rank[j];
-      s_keys[pos] = keys[j];
-      if (HASV) s_vals[pos] = vals[j];
-    }
+    pos[j] = s_lstart[dig[j]] + s_wc[w][dig[j]] + rank[j];
+    if (wbase + j * 64 + lane < tile_n) s_stage[pos[j]] = keys[j];
   }
   __syncthreads();
   for (u32 i = tid; i < tile_n; i += SORT_NT) {
-    const K k = s_keys[i];
-    const u64 o = s_gbase[(u32)(k >> shift) & (RADIX - 1)] + i;
-    dst[o] = k;
-    if (HASV) dstv[o] = s_vals[i];
+    const K k = s_stage[i];
+    const u32 d = (u32)(k >> shift) & (RADIX - 1);
+    dst[s_gbase[d] + i] = k;
+    if (HASV) s_dig[i] = (uint8_t)d;
+  }
+  if (HASV) {
+    __syncthreads();
+    u32* sv = (u32*)s_stage;
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j)
+      if (wbase + j * 64 + lane < tile_n) sv[pos[j]] = vals[j];
+    __syncthreads();
+    for (u32 i = tid; i < tile_n; i += SORT_NT) dstv[s_gbase[s_dig[i]] + i] = sv[i];
   }
 }
 

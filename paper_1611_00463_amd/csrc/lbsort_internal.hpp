@@ -30,6 +30,8 @@ enum Counter : int {
   C_ERR = 0,        // device error bits (sticky until lbsort_check)
   C_NSMALL = 1,     // number of blocks sorted whole in LDS
   C_TILE0 = 2,      // C_TILE0 + pass: ordered tile ids of radix pass `pass`
+  C_NLARGE = 12,    // blocks larger than one tile
+  C_RMIN = 13,      // fewest tiles of any large block
   C_COUNT = 32
 };
 enum DevErr : u32 {
@@ -52,6 +54,8 @@ struct Plan {
   u64* blk_start;        // [NB+1]
   u32* tstart;           // [NB+1] radix tile prefix (blocks larger than one tile)
   u32* small_list;       // [NB]
+  u32* large_list;       // [NB] blocks larger than one tile, in block order
+  u32* rem_prefix;       // [NB+1] over large blocks: prefix of (tiles - C_RMIN)
   u32* counters;         // [C_COUNT]
   u32* hist;             // [NB][D][256]
   u64* status;           // [max_tiles][256]
@@ -65,9 +69,15 @@ struct Plan {
   u64* G;                // [B][P+1]
   void* splitters;       // [B][P-1]
   u32* mtile;            // [NGmax+1] merge tile prefix of the current level
-  u64* mcut;             // [slots][F] merge tile boundary cuts
+  u64* rec_start;        // [mtiles][F] per merge tile: first source element of each run
+  u64* rec_end;          // [mtiles][F] per merge tile: one past the last
+  u64* rec_out;          // [mtiles]    per merge tile: first output position
+  u32* rec_n;            // [mtiles]    per merge tile: element count
+  u32* slot_grp;         // [mtiles+NGmax] merge boundary slot -> group
+  u64* grp_run;          // [NGmax][F][2] per group and input run: source offset, length
+  u64* grp_out;          // [NGmax][2]    per group: output offset, length
   u32 ng_max;            // merge groups, worst case over levels
-  u32 mslots_max;        // merge boundary slots, worst case
+  u32 mtiles_max;        // merge tiles, worst case over levels
 };
 
 // ----------------------------------------------------------------- helpers
@@ -128,6 +138,30 @@ __device__ inline u64 block_begin(const u64* seg, u32 b, u32 i, u32 P) {
   u64 a = seg[b], n = seg[b + 1] - seg[b];
   return a + (u64)(((unsigned __int128)i * n) / P);
 }
+
+// Order of the radix tiles.  The first rmin tiles of every large block are
+// interleaved across blocks (id = lt * nlarge + j for the j-th large block), so
+// that the tiles in flight at one time belong to many blocks and every block's
+// look-back chain stays short; the remaining tiles follow block by block.
+struct TileOrder {
+  u32 nlarge, rmin;
+  const u32* large_list;
+  const u32* rem_prefix;
+  __device__ inline void locate(u32 id, u32& j, u32& lt) const {
+    const u32 head = nlarge * rmin;
+    if (id < head) {
+      j = id % nlarge;
+      lt = id / nlarge;
+    } else {
+      const u32 x = id - head;
+      j = find_seg(rem_prefix, nlarge, x);
+      lt = rmin + (x - rem_prefix[j]);
+    }
+  }
+  __device__ inline u32 id_of(u32 j, u32 lt) const {
+    return lt < rmin ? lt * nlarge + j : nlarge * rmin + rem_prefix[j] + (lt - rmin);
+  }
+};
 
 // Optional per-launch event timing (lbsort_profile_enable).
 int prof_begin(hipStream_t s);

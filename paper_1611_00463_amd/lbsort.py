@@ -38,7 +38,7 @@ class Parts(ctypes.Structure):
 
 EXPORTS = ("lbsort_sort_keys", "lbsort_sort_pairs", "lbsort_sort_batch", "lbsort_local_sort",
            "lbsort_check", "lbsort_status_string", "lbsort_last_error", "lbsort_autotune",
-           "lbsort_load_tuning")
+           "lbsort_load_tuning", "lbsort_profile_enable", "lbsort_profile_read")
 
 _lib = None
 
@@ -69,6 +69,8 @@ def load(path: str = LIB_PATH):
     lib.lbsort_last_error.restype = ctypes.c_char_p
     lib.lbsort_autotune.argtypes = [i32, i32, u64, u32, u32, ctypes.c_char_p, ctypes.POINTER(u32), ctypes.POINTER(u32)]
     lib.lbsort_load_tuning.argtypes = [ctypes.c_char_p]
+    lib.lbsort_profile_enable.argtypes = [i32]
+    lib.lbsort_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.lbsort_status_string.restype = ctypes.c_char_p

@@ -1,0 +1,71 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (2^28 keys, P = 64, 512 samples per block, default fan-in and tile).
+
+The whole oracle merge would take minutes on the CPU, so:
+* the partition metadata (splitters, cut matrix, send counts, offsets) is
+  computed by the oracle's own step functions and compared bit for bit;
+* the sorted output is checked by properties that pin it uniquely: keys
+  non-decreasing, (key, value) pairs a permutation of the input (values are
+  the input indices), and equal keys in increasing index order (stable);
+  for keys only, the multiset of keys is compared instead.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sample_sort as O
+from paper_1611_00463_amd import datagen
+from paper_1611_00463_amd import lbsort as L
+from tests.parity import assert_same, u64
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 28
+P, S = 64, 512
+SIGN = -(1 << 63)
+
+
+def signed(t):
+    """Order-preserving view of uint64 as int64 (flip the top bit)."""
+    return t.view(torch.int64) ^ SIGN
+
+
+def check_metadata(r, keys_np, mode=O.INV_COUNT):
+    plan = O.partition_plan(keys_np, P, S, mode)
+    assert_same("splitters", r.splitters.cpu().numpy()[0], plan["splitters"])
+    assert_same("cuts", u64(r.cuts)[0], plan["cuts"].astype(np.uint64))
+    assert_same("send_counts", u64(r.send_counts)[0], plan["send_counts"].astype(np.uint64))
+    assert_same("part_offsets", u64(r.part_offsets)[0], plan["part_offsets"].astype(np.uint64))
+    return plan
+
+
+def test_pairs_full_size():
+    keys = datagen.uniform_keys_torch(N, 2, "cuda")
+    vals = datagen.index_values_torch(N, "cuda")
+    r = L.sort_pairs(keys, vals, P, s=S, want_send=True, want_cuts=True)
+    L.check(r.workspace)
+    ko, vo = signed(r.keys), r.vals.view(torch.int32).to(torch.int64)
+    assert bool((ko[1:] >= ko[:-1]).all()), "keys not sorted"
+    assert bool((torch.bincount(vo, minlength=N) == 1).all()), "values are not a permutation"
+    assert bool((r.keys.view(torch.int64) == keys.view(torch.int64)[vo]).all()), "pairs broken"
+    eq = ko[1:] == ko[:-1]
+    assert bool((vo[1:][eq] > vo[:-1][eq]).all()), "not stable"
+    del ko, vo, eq
+    check_metadata(r, keys.cpu().numpy())
+    counts = r.part_counts.cpu().numpy()[0]
+    assert counts.max() / counts.mean() <= 1.05
+
+
+def test_duplicate_heavy_full_size():
+    keys_np = datagen.duplicate_heavy_keys(N, seed=3)
+    keys = torch.from_numpy(keys_np).cuda()
+    r = L.sort_keys(keys, P, s=S, want_send=True, want_cuts=True)
+    L.check(r.workspace)
+    ko = signed(r.keys)
+    assert bool((ko[1:] >= ko[:-1]).all()), "keys not sorted"
+    ui, ci = torch.unique(signed(keys), return_counts=True)
+    uo, co = torch.unique_consecutive(ko, return_counts=True)
+    assert torch.equal(ui, uo) and torch.equal(ci, co), "output is not a permutation of the input"
+    plan = check_metadata(r, keys_np)
+    counts = plan["part_counts"]
+    assert counts.max() / counts.mean() <= 1.05, "investigator lost the balance"
