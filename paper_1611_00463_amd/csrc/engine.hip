@@ -50,6 +50,21 @@ __global__ void k_seg2(u64* seg, u64 n) {
 
 static inline u64 align256(u64 x) { return (x + 255) & ~(u64)255; }
 
+// Compute units of the current device (cached per device).
+static u32 device_cus() {
+  static int cached_dev = -1;
+  static u32 cached = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev != cached_dev) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cached = (u32)cus;
+    cached_dev = dev;
+  }
+  return cached;
+}
+
 struct Shape {
   int key_type, val_type;
   u32 B, P, s, inv, F, TM, L, D;
@@ -198,6 +213,8 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.L = sh.L;
   p.TM = sh.TM;
   p.max_tiles = (u32)sh.max_tiles;
+  p.nq = NQ;
+  p.persist_wgs = device_cus() * 4;
   p.total_n = sh.total_n;
   p.blk_start = (u64*)(ws + lay.blk_start);
   p.tstart = (u32*)(ws + lay.tstart);

@@ -285,13 +285,44 @@ __global__ __launch_bounds__(256) void k_partition(Plan p, Level L, const K* __r
 }
 
 // ----------------------------------------------------------------- merge tile
+// Sequential merge of outputs [q, qend) of the pair A = [a0, a1), B = [a1, b1)
+// (both sorted, ties to A) starting at diagonal q - a0.  The two candidates
+// stay in registers, so each output costs one LDS read of the side consumed.
+template <typename K, bool IDX>
+__device__ inline void merge_run(const K* ck, const uint16_t* ci, K* nk, uint16_t* ni, u32 a0, u32 a1, u32 b1,
+                                 u32 q, u32 qend) {
+  const u32 la = a1 - a0, lb = b1 - a1;
+  const u32 diag = q - a0;
+  u32 lo = diag > lb ? diag - lb : 0, hi = diag < la ? diag : la;
+  while (lo < hi) {
+    const u32 mid = (lo + hi) >> 1;
+    if (ck[a0 + mid] <= ck[a1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
+  }
+  u32 ia = a0 + lo, ib = a1 + diag - lo;
+  K ka = ia < a1 ? ck[ia] : (K)0, kb = ib < b1 ? ck[ib] : (K)0;
+  for (; q < qend; ++q) {
+    const bool takeA = ib >= b1 || (ia < a1 && ka <= kb);
+    if (takeA) {
+      nk[q] = ka;
+      if (IDX) ni[q] = ci[ia];
+      ++ia;
+      ka = ia < a1 ? ck[ia] : (K)0;
+    } else {
+      nk[q] = kb;
+      if (IDX) ni[q] = ci[ib];
+      ++ib;
+      kb = ib < b1 ? ck[ib] : (K)0;
+    }
+  }
+}
+
 template <typename K, bool HASV, int F, int TM>
 __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restrict__ src,
                                                const u32* __restrict__ srcv, K* __restrict__ dst,
                                                u32* __restrict__ dstv) {
   constexpr int NT = 256, IT = TM / NT;
   __shared__ K s_k[2][TM];
-  __shared__ uint16_t s_i[2][TM];
+  __shared__ uint16_t s_i[HASV ? 2 : 1][HASV ? TM : 1];
   __shared__ u32 s_v[HASV ? TM : 1];
   __shared__ u64 s_roff[F];
   __shared__ u32 s_so[F + 1];
@@ -318,23 +349,22 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
   }
   __syncthreads();
   const u32 n = s_so[F];
-  for (u32 q = tid; q < n; q += NT) {
+  {
     u32 r = 0;
-#pragma unroll
-    for (int x = 1; x < F; ++x) r += (q >= s_so[x]) ? 1u : 0u;
-    const u64 e = s_roff[r] + (q - s_so[r]);
-    s_k[0][q] = src[e];
-    s_i[0][q] = (uint16_t)q;
-    if (HASV) s_v[q] = srcv[e];
+    for (u32 q = tid; q < n; q += NT) {
+      while (r + 1 < (u32)F && q >= s_so[r + 1]) ++r;
+      const u64 e = s_roff[r] + (q - s_so[r]);
+      s_k[0][q] = src[e];
+      if (HASV) {
+        s_i[0][q] = (uint16_t)q;
+        s_v[q] = srcv[e];
+      }
+    }
   }
   __syncthreads();
   int cur = 0;
 #pragma unroll
   for (int w = 1; w < F; w <<= 1) {
-    const K* ck = s_k[cur];
-    const uint16_t* ci = s_i[cur];
-    K* nk = s_k[cur ^ 1];
-    uint16_t* ni = s_i[cur ^ 1];
     u32 q = tid * IT;
     const u32 qend = q + IT < n ? q + IT : n;
     while (q < qend) {
@@ -345,27 +375,10 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
       const u32 a0 = s_so[2 * j * w];
       const u32 a1 = s_so[min((u32)((2 * j + 1) * w), (u32)F)];
       const u32 b1 = s_so[min((u32)((2 * j + 2) * w), (u32)F)];
-      const u32 la = a1 - a0, lb = b1 - a1;
-      const u32 diag = q - a0;
-      u32 lo = diag > lb ? diag - lb : 0, hi = diag < la ? diag : la;
-      while (lo < hi) {
-        const u32 mid = (lo + hi) >> 1;
-        if (ck[a0 + mid] <= ck[a1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
-      }
-      u32 ia = a0 + lo, ib = a1 + diag - lo;
       const u32 sub_end = qend < b1 ? qend : b1;
-      for (; q < sub_end; ++q) {
-        const bool takeA = ib >= b1 || (ia < a1 && ck[ia] <= ck[ib]);
-        if (takeA) {
-          nk[q] = ck[ia];
-          ni[q] = ci[ia];
-          ++ia;
-        } else {
-          nk[q] = ck[ib];
-          ni[q] = ci[ib];
-          ++ib;
-        }
-      }
+      merge_run<K, HASV>(s_k[cur], s_i[HASV ? cur : 0], s_k[cur ^ 1], s_i[HASV ? cur ^ 1 : 0], a0, a1, b1, q,
+                         sub_end);
+      q = sub_end;
     }
     __syncthreads();
     cur ^= 1;

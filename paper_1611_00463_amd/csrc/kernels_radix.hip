@@ -89,7 +89,6 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
     u64 ex = block_exclusive_scan<1024>(tiles, s_w, tot);
     if (idx < p.NB) p.tstart[idx] = (u32)(carry_t + ex);
     carry_t += tot;
-    if (tiles) atomicMin(&s_rmin, (u32)tiles);
     ex = block_exclusive_scan<1024>(tiles ? 1 : 0, s_w, tot);
     if (tiles) p.large_list[carry_l + ex] = idx;
     carry_l += tot;
@@ -102,28 +101,51 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
   }
   if (tid == 0) p.tstart[p.NB] = (u32)carry_t;
   __syncthreads();
-  const u32 rmin = carry_l ? s_rmin : 0;
-  // prefix over large blocks of the tiles beyond the interleaved head
-  u64 carry_r = 0;
-  for (u32 base = 0; base < (u32)carry_l; base += 1024) {
-    const u32 j = base + tid;
-    u64 extra = 0;
-    if (j < (u32)carry_l) {
-      const u32 blk = p.large_list[j];
-      extra = (u64)(p.tstart[blk + 1] - p.tstart[blk]) - rmin;
+  // Tile queues: large block j goes to queue j % nq.  Per queue: block count,
+  // fewest tiles (rmin), prefix of the tiles beyond the interleaved head, and
+  // the queue's first slot in the look-back status array.
+  const u32 nl = (u32)carry_l;
+  const u32 nq = p.nq;
+  u64 qbase = 0;
+  for (u32 x = 0; x < nq; ++x) {
+    const u32 nbx = nl > x ? (nl - x + nq - 1) / nq : 0;
+    if (tid == 0) s_rmin = 0xFFFFFFFFu;
+    __syncthreads();
+    for (u32 jx = tid; jx < nbx; jx += 1024) {
+      const u32 blk = p.large_list[x + nq * jx];
+      atomicMin(&s_rmin, p.tstart[blk + 1] - p.tstart[blk]);
     }
-    u64 tot;
-    const u64 ex = block_exclusive_scan<1024>(extra, s_w, tot);
-    if (j < (u32)carry_l) p.rem_prefix[j] = (u32)(carry_r + ex);
-    carry_r += tot;
+    __syncthreads();
+    const u32 rmin = nbx ? s_rmin : 0;
+    u64 carry_r = 0, carry_q = 0;
+    for (u32 base = 0; base < nbx; base += 1024) {
+      const u32 jx = base + tid;
+      u64 tiles = 0;
+      if (jx < nbx) {
+        const u32 blk = p.large_list[x + nq * jx];
+        tiles = p.tstart[blk + 1] - p.tstart[blk];
+      }
+      u64 tot, totq;
+      const u64 ex = block_exclusive_scan<1024>(tiles ? tiles - rmin : 0, s_w, tot);
+      block_exclusive_scan<1024>(tiles, s_w, totq);
+      if (jx < nbx) p.rem_prefix[x + nq * jx] = (u32)(carry_r + ex);
+      carry_r += tot;
+      carry_q += totq;
+    }
+    if (tid == 0) {
+      p.counters[C_QPARAM + 4 * x + 0] = nbx;
+      p.counters[C_QPARAM + 4 * x + 1] = rmin;
+      p.counters[C_QPARAM + 4 * x + 2] = (u32)qbase;
+      p.counters[C_QPARAM + 4 * x + 3] = (u32)carry_q;
+    }
+    qbase += carry_q;
+    __syncthreads();
   }
   if (tid == 0) {
-    p.rem_prefix[carry_l] = (u32)carry_r;
     p.samp_start[p.NB] = carry_s;
     p.blk_start[p.NB] = bad ? 0 : p.seg[p.B];
     p.counters[C_NSMALL] = (u32)carry_m;
-    p.counters[C_NLARGE] = (u32)carry_l;
-    p.counters[C_RMIN] = rmin;
+    p.counters[C_NLARGE] = nl;
   }
 }
 
@@ -132,49 +154,68 @@ __global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
 }
 
 // ----------------------------------------------------------------- histogram
-// Digit counts of all passes for every tile of a large block, accumulated per
-// block.  Equal keys inside a wave are first merged (a few leader rounds) so
-// that heavy duplicates do not serialise on one LDS counter.
+// Digit counts of all passes for the tiles of large blocks, accumulated per
+// block.  A workgroup covers HIST_TILES consecutive tiles (block-contiguous
+// numbering) and flushes its LDS counts to the block's global counts when the
+// block changes, so global atomics are few.  Equal keys inside a wave are
+// first merged (a few leader rounds) so that heavy duplicates do not
+// serialise on one LDS counter.
+constexpr u32 HIST_TILES = 16;
+
 template <typename K>
 __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ src) {
   constexpr int D = KeyT<K>::BITS / RADIX_BITS;
   __shared__ u32 h[D * RADIX];
   __shared__ u32 s_blk;
   const u32 tid = threadIdx.x, lane = tid & 63;
-  const u32 t = blockIdx.x;
   const u32 total = p.tstart[p.NB];
-  if (t >= total) return;
+  const u32 t_begin = blockIdx.x * HIST_TILES;
+  if (t_begin >= total) return;
+  const u32 t_end = t_begin + HIST_TILES < total ? t_begin + HIST_TILES : total;
   for (int i = tid; i < D * RADIX; i += SORT_NT) h[i] = 0;
-  if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t);
+  if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t_begin);
   __syncthreads();
-  const u32 blk = s_blk;
-  const u64 tbase = p.blk_start[blk] + (u64)(t - p.tstart[blk]) * SORT_TILE;
-  const u64 rem = p.blk_start[blk + 1] - tbase;
-  const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
-#pragma unroll 4
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const u32 idx = j * SORT_NT + tid;
-    const bool valid = idx < tile_n;
-    const K key = valid ? src[tbase + idx] : (K)0;
-    bool done = !valid;
-    for (int r = 0; r < 3; ++r) {
-      const u64 act = __ballot(!done);
-      if (act == 0) break;
-      const int leader = __ffsll((unsigned long long)act) - 1;
-      const K lk = __shfl(key, leader);
-      const bool same = !done && key == lk;
-      const u64 sm = __ballot(same);
-      if (__popcll(sm) < 2) break;  // no duplicate of the leader: leave all to the bulk path
-      if (lane == (u32)leader) {
-        const u32 c = (u32)__popcll(sm);
-#pragma unroll
-        for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((lk >> (q * RADIX_BITS)) & (RADIX - 1))], c);
+  u32 blk = s_blk;
+  for (u32 t = t_begin; t < t_end; ++t) {
+    if (t >= p.tstart[blk + 1]) {
+      // next block: flush the counts of this one
+      __syncthreads();
+      u32* gh = p.hist + (u64)blk * D * RADIX;
+      for (int i = tid; i < D * RADIX; i += SORT_NT) {
+        if (h[i]) atomicAdd(&gh[i], h[i]);
+        h[i] = 0;
       }
-      done = done || same;
+      while (t >= p.tstart[blk + 1]) ++blk;
+      __syncthreads();
     }
-    if (!done) {
+    const u64 tbase = p.blk_start[blk] + (u64)(t - p.tstart[blk]) * SORT_TILE;
+    const u64 rem = p.blk_start[blk + 1] - tbase;
+    const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+#pragma unroll 4
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const u32 idx = j * SORT_NT + tid;
+      const bool valid = idx < tile_n;
+      const K key = valid ? src[tbase + idx] : (K)0;
+      bool done = !valid;
+      for (int r = 0; r < 3; ++r) {
+        const u64 act = __ballot(!done);
+        if (act == 0) break;
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const K lk = __shfl(key, leader);
+        const bool same = !done && key == lk;
+        const u64 sm = __ballot(same);
+        if (__popcll(sm) < 2) break;  // no duplicate of the leader: leave all to the bulk path
+        if (lane == (u32)leader) {
+          const u32 c = (u32)__popcll(sm);
 #pragma unroll
-      for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1))], 1u);
+          for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((lk >> (q * RADIX_BITS)) & (RADIX - 1))], c);
+        }
+        done = done || same;
+      }
+      if (!done) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1))], 1u);
+      }
     }
   }
   __syncthreads();
@@ -210,8 +251,8 @@ __global__ __launch_bounds__(256) void k_scan_hist(Plan p) {
 // Items are laid out wave-major: item j of lane l of wave w is tile position
 // w*64*ITEMS + j*64 + l, so processing j in order and lanes in order inside a
 // wave keeps the ranking stable.  wc: this wave's 256 digit counters.
-template <typename K, int ITEMS>
-__device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n, u32 shift, u32* wc,
+template <typename K, int ITEMS, typename C>
+__device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n, u32 shift, C* wc,
                                   u32 (&rank)[ITEMS], u32 (&dig)[ITEMS]) {
   const u32 lane = threadIdx.x & 63;
 #pragma unroll
@@ -228,129 +269,140 @@ __device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n,
     const u32 below = count_below(m);
     u32 base = 0;
     if (valid) base = wc[d];
-    if (valid && below == 0) wc[d] = base + (u32)__popcll(m);
+    if (valid && below == 0) wc[d] = (C)(base + (u32)__popcll(m));
     rank[j] = base + below;
     dig[j] = d;
   }
 }
 
 // ----------------------------------------------------------------- one pass
+// Persistent workgroups: workgroup w serves queue w % nq first (the hardware
+// hands workgroups to the XCDs round-robin), then helps the other queues.
+// A tile waits only for tiles of its own queue with smaller tickets, which
+// running workgroups hold, so the waits always end.
 template <typename K, bool HASV>
-__global__ __launch_bounds__(SORT_NT) void k_onesweep(Plan p, const K* __restrict__ src,
+__global__ __launch_bounds__(SORT_NT, HASV ? 3 : 4) void k_onesweep(Plan p, const K* __restrict__ src,
                                                       const u32* __restrict__ srcv, K* __restrict__ dst,
                                                       u32* __restrict__ dstv, u32 pass) {
   constexpr int NWV = SORT_NT / 64, WI = 64 * SORT_ITEMS;
   static_assert(SORT_NT == RADIX, "one thread per digit");
-  __shared__ u32 s_wc[NWV][RADIX];
-  __shared__ u64 s_gbase[RADIX];
-  __shared__ u32 s_lstart[RADIX];
+  // LDS kept under 40 KB so that four workgroups fit on a compute unit:
+  // 16-bit per-wave digit counters (they end up holding the tile-local start
+  // of each wave's run of a digit), 32-bit block-relative write bases, keys
+  // staged in s_stage and values in the same buffer afterwards, and s_dig
+  // holding each staged position's digit for the value write.
+  __shared__ uint16_t s_wc[NWV][RADIX];
+  __shared__ u32 s_gbase[RADIX];
   __shared__ u64 s_scan[NWV];
-  // Keys are staged in s_stage; values reuse the same buffer afterwards, and
-  // s_dig keeps each staged position's digit for the value write.
   __shared__ K s_stage[SORT_TILE];
   __shared__ uint8_t s_dig[HASV ? SORT_TILE : 1];
-  __shared__ u32 s_info[3];
+  __shared__ u32 s_ticket;
   const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const u32 shift = pass * RADIX_BITS;
-  const u32 total = p.tstart[p.NB];
-  const TileOrder ord{p.counters[C_NLARGE], p.counters[C_RMIN], p.large_list, p.rem_prefix};
-  if (tid == 0) {
-    const u32 t = atomicAdd(&p.counters[C_TILE0 + pass], 1u);
-    s_info[0] = t;
-    u32 j = 0, lt = 0;
-    if (t < total) ord.locate(t, j, lt);
-    s_info[1] = j;
-    s_info[2] = lt;
-  }
-  for (int i = tid; i < NWV * RADIX; i += SORT_NT) (&s_wc[0][0])[i] = 0;
-  __syncthreads();
-  const u32 t = s_info[0];
-  if (t >= total) return;
-  const u32 jl = s_info[1];
-  const u32 lt = s_info[2];
-  const u32 blk = p.large_list[jl];
-  const u64 bstart = p.blk_start[blk];
-  const u64 tbase = bstart + (u64)lt * SORT_TILE;
-  const u64 rem = p.blk_start[blk + 1] - tbase;
-  const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
-  const u32 wbase = w * WI;
-
-  K keys[SORT_ITEMS];
-  u32 vals[HASV ? SORT_ITEMS : 1];
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const u32 idx = wbase + j * 64 + lane;
-    if (idx < tile_n) {
-      keys[j] = src[tbase + idx];
-      if (HASV) vals[j] = srcv[tbase + idx];
-    } else {
-      keys[j] = 0;
-      if (HASV) vals[j] = 0;
-    }
-  }
-  u32 rank[SORT_ITEMS], dig[SORT_ITEMS];
-  rank_items<K, SORT_ITEMS>(keys, wbase, tile_n, shift, s_wc[w], rank, dig);
-  __syncthreads();
-
-  // Per-digit tile count; per-wave counters become exclusive wave prefixes.
-  u32 tot = 0;
-#pragma unroll
-  for (int v = 0; v < NWV; ++v) {
-    const u32 c = s_wc[v][tid];
-    s_wc[v][tid] = tot;
-    tot += c;
-  }
-  // Decoupled look-back over the earlier tiles of this block, digit = tid.
   const u32 epoch = pass + 1;
-  u64* st = p.status + (u64)t * RADIX + tid;
-  u64 excl = 0;
-  if (lt == 0) {
-    st_release_agent(st, st_pack(epoch, ST_INC, tot));
-  } else {
-    st_release_agent(st, st_pack(epoch, ST_AGG, tot));
-    u32 plt = lt - 1, spins = 0;
+  const u32 nq = p.nq;
+  for (u32 qi = 0; qi < nq; ++qi) {
+    const u32 x = (blockIdx.x + qi) % nq;
+    const TileQueue Q{x, nq, p.counters[C_QPARAM + 4 * x], p.counters[C_QPARAM + 4 * x + 1], p.rem_prefix};
+    const u32 qbase = p.counters[C_QPARAM + 4 * x + 2];
+    const u32 qtiles = p.counters[C_QPARAM + 4 * x + 3];
     while (true) {
-      const u64 v = ld_acquire_agent(p.status + (u64)ord.id_of(jl, plt) * RADIX + tid);
-      if ((u32)(v >> 56) != epoch) {
-        if (++spins > SPIN_LIMIT) {
-          set_error(p.counters, E_SPIN);
-          break;
+      __syncthreads();
+      if (tid == 0) s_ticket = atomicAdd(&p.counters[C_TICKET + nq * pass + x], 1u);
+      for (int i = tid; i < NWV * RADIX; i += SORT_NT) (&s_wc[0][0])[i] = 0;
+      __syncthreads();
+      const u32 t = s_ticket;
+      if (t >= qtiles) break;
+      u32 jx, lt;
+      Q.locate(t, jx, lt);
+      const u32 blk = p.large_list[x + nq * jx];
+      const u64 bstart = p.blk_start[blk];
+      const u64 tbase = bstart + (u64)lt * SORT_TILE;
+      const u64 rem = p.blk_start[blk + 1] - tbase;
+      const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+      const u32 wbase = w * WI;
+
+      K keys[SORT_ITEMS];
+      u32 vals[HASV ? SORT_ITEMS : 1];
+#pragma unroll
+      for (int j = 0; j < SORT_ITEMS; ++j) {
+        const u32 idx = wbase + j * 64 + lane;
+        if (idx < tile_n) {
+          keys[j] = src[tbase + idx];
+          if (HASV) vals[j] = srcv[tbase + idx];
+        } else {
+          keys[j] = 0;
+          if (HASV) vals[j] = 0;
         }
-        __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      excl += v & ST_VALMASK;
-      if (((v >> 54) & 3u) == ST_INC || plt == 0) break;
-      --plt;
+      u32 rank[SORT_ITEMS];
+      {
+        u32 dig[SORT_ITEMS];
+        rank_items<K, SORT_ITEMS, uint16_t>(keys, wbase, tile_n, shift, s_wc[w], rank, dig);
+      }
+      __syncthreads();
+
+      // Per-digit tile count; per-wave counters become exclusive wave prefixes.
+      u32 tot = 0, wpre[NWV];
+#pragma unroll
+      for (int v = 0; v < NWV; ++v) {
+        wpre[v] = tot;
+        tot += s_wc[v][tid];
+      }
+      // Decoupled look-back over the earlier tiles of this block, digit = tid.
+      u64* st = p.status + (u64)(qbase + t) * RADIX + tid;
+      u64 excl = 0;
+      if (lt == 0) {
+        st_release_agent(st, st_pack(epoch, ST_INC, tot));
+      } else {
+        st_release_agent(st, st_pack(epoch, ST_AGG, tot));
+        u32 plt = lt - 1, spins = 0;
+        while (true) {
+          const u64 v = ld_acquire_agent(p.status + (u64)(qbase + Q.id_of(jx, plt)) * RADIX + tid);
+          if ((u32)(v >> 56) != epoch) {
+            if (++spins > SPIN_LIMIT) {
+              set_error(p.counters, E_SPIN);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          excl += v & ST_VALMASK;
+          if (((v >> 54) & 3u) == ST_INC || plt == 0) break;
+          --plt;
+        }
+        st_release_agent(st, st_pack(epoch, ST_INC, excl + tot));
+      }
+      u64 ttot;
+      const u32 lstart = (u32)block_exclusive_scan<SORT_NT>(tot, s_scan, ttot);
+#pragma unroll
+      for (int v = 0; v < NWV; ++v) s_wc[v][tid] = (uint16_t)(lstart + wpre[v]);
+      s_gbase[tid] = (u32)(p.hist[((u64)blk * p.D + pass) * RADIX + tid] + excl - lstart);
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < SORT_ITEMS; ++j) {
+        rank[j] += s_wc[w][(u32)(keys[j] >> shift) & (RADIX - 1)];  // rank[] now holds the staged position
+        if (wbase + j * 64 + lane < tile_n) s_stage[rank[j]] = keys[j];
+      }
+      __syncthreads();
+      K* dblk = dst + bstart;
+      for (u32 i = tid; i < tile_n; i += SORT_NT) {
+        const K k = s_stage[i];
+        const u32 d = (u32)(k >> shift) & (RADIX - 1);
+        dblk[s_gbase[d] + i] = k;
+        if (HASV) s_dig[i] = (uint8_t)d;
+      }
+      if (HASV) {
+        __syncthreads();
+        u32* sv = (u32*)s_stage;
+#pragma unroll
+        for (int j = 0; j < SORT_ITEMS; ++j)
+          if (wbase + j * 64 + lane < tile_n) sv[rank[j]] = vals[j];
+        __syncthreads();
+        u32* vblk = dstv + bstart;
+        for (u32 i = tid; i < tile_n; i += SORT_NT) vblk[s_gbase[s_dig[i]] + i] = sv[i];
+      }
     }
-    st_release_agent(st, st_pack(epoch, ST_INC, excl + tot));
-  }
-  u64 ttot;
-  const u32 lstart = (u32)block_exclusive_scan<SORT_NT>(tot, s_scan, ttot);
-  s_lstart[tid] = lstart;
-  s_gbase[tid] = bstart + p.hist[((u64)blk * p.D + pass) * RADIX + tid] + excl - lstart;
-  __syncthreads();
-  u32 pos[SORT_ITEMS];
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    pos[j] = s_lstart[dig[j]] + s_wc[w][dig[j]] + rank[j];
-    if (wbase + j * 64 + lane < tile_n) s_stage[pos[j]] = keys[j];
-  }
-  __syncthreads();
-  for (u32 i = tid; i < tile_n; i += SORT_NT) {
-    const K k = s_stage[i];
-    const u32 d = (u32)(k >> shift) & (RADIX - 1);
-    dst[s_gbase[d] + i] = k;
-    if (HASV) s_dig[i] = (uint8_t)d;
-  }
-  if (HASV) {
-    __syncthreads();
-    u32* sv = (u32*)s_stage;
-#pragma unroll
-    for (int j = 0; j < SORT_ITEMS; ++j)
-      if (wbase + j * 64 + lane < tile_n) sv[pos[j]] = vals[j];
-    __syncthreads();
-    for (u32 i = tid; i < tile_n; i += SORT_NT) dstv[s_gbase[s_dig[i]] + i] = sv[i];
   }
 }
 
@@ -387,7 +439,7 @@ __global__ __launch_bounds__(SORT_NT) void k_small_sort(Plan p, const K* __restr
     for (int i = tid; i < NWV * RADIX; i += SORT_NT) (&s_wc[0][0])[i] = 0;
     __syncthreads();
     u32 rank[SORT_ITEMS], dig[SORT_ITEMS];
-    rank_items<K, SORT_ITEMS>(keys, wbase, n, shift, s_wc[w], rank, dig);
+    rank_items<K, SORT_ITEMS, u32>(keys, wbase, n, shift, s_wc[w], rank, dig);
     __syncthreads();
     u32 tot = 0;
 #pragma unroll
@@ -437,7 +489,7 @@ void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s) {
 template <typename K>
 void launch_hist(const Plan& p, const K* src, hipStream_t s) {
   if (p.max_tiles == 0) return;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_hist<K>, dim3(p.max_tiles), dim3(SORT_NT), 0, s, p, src); prof_end(pe_, "hist", s); }
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_hist<K>, dim3((p.max_tiles + HIST_TILES - 1) / HIST_TILES), dim3(SORT_NT), 0, s, p, src); prof_end(pe_, "hist", s); }
   const u32 waves = p.NB * p.D;
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_scan_hist, dim3((waves + 3) / 4), dim3(256), 0, s, p); prof_end(pe_, "scan_hist", s); }
 }
@@ -450,7 +502,10 @@ void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32
 template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s) {
   if (p.max_tiles == 0) return;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV>), dim3(p.max_tiles), dim3(SORT_NT), 0, s, p, src, srcv, dst, dstv,
+  // persistent grid: a few workgroups per compute unit, a multiple of the queue count
+  u32 grid = p.persist_wgs < p.max_tiles ? p.persist_wgs : p.max_tiles;
+  grid = (grid + p.nq - 1) / p.nq * p.nq;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV>), dim3(grid), dim3(SORT_NT), 0, s, p, src, srcv, dst, dstv,
                      pass); prof_end(pe_, "onesweep", s); }
 }
 

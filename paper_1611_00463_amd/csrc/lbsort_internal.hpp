@@ -26,13 +26,14 @@ __host__ __device__ inline u64 st_pack(u32 epoch, u64 flag, u64 v) {
 }
 
 // Slots of the small counter array at the head of the workspace.
+constexpr int NQ = 8;  // radix tile queues, one per XCD of the MI355X
 enum Counter : int {
   C_ERR = 0,        // device error bits (sticky until lbsort_check)
   C_NSMALL = 1,     // number of blocks sorted whole in LDS
-  C_TILE0 = 2,      // C_TILE0 + pass: ordered tile ids of radix pass `pass`
-  C_NLARGE = 12,    // blocks larger than one tile
-  C_RMIN = 13,      // fewest tiles of any large block
-  C_COUNT = 32
+  C_NLARGE = 2,     // blocks larger than one tile
+  C_QPARAM = 8,     // C_QPARAM + 4x + {0: blocks, 1: rmin, 2: first status slot, 3: tiles} of queue x
+  C_TICKET = 64,    // C_TICKET + NQ * pass + x: next ticket of queue x in radix pass `pass`
+  C_COUNT = 128
 };
 enum DevErr : u32 {
   E_SPIN = 1u,         // a decoupled look-back wait gave up
@@ -49,6 +50,8 @@ struct Plan {
   u32 inv;               // investigator mode
   u32 F, L, TM;          // merge fan-in, merge levels, merge tile
   u32 max_tiles;         // radix tiles, worst case
+  u32 nq;                // radix tile queues (NQ, or 1)
+  u32 persist_wgs;       // workgroups of the persistent radix pass
   u64 total_n;
   const u64* seg;        // [B+1]
   u64* blk_start;        // [NB+1]
@@ -139,27 +142,36 @@ __device__ inline u64 block_begin(const u64* seg, u32 b, u32 i, u32 P) {
   return a + (u64)(((unsigned __int128)i * n) / P);
 }
 
-// Order of the radix tiles.  The first rmin tiles of every large block are
-// interleaved across blocks (id = lt * nlarge + j for the j-th large block), so
-// that the tiles in flight at one time belong to many blocks and every block's
-// look-back chain stays short; the remaining tiles follow block by block.
-struct TileOrder {
-  u32 nlarge, rmin;
-  const u32* large_list;
-  const u32* rem_prefix;
-  __device__ inline void locate(u32 id, u32& j, u32& lt) const {
-    const u32 head = nlarge * rmin;
+// Order of the radix tiles.  Large block j (in block order) belongs to queue
+// j % nq at index jx = j / nq; each queue has its own ticket counter and is
+// meant to be served by the workgroups of one XCD, so that a block's tiles,
+// its look-back chain and the partial cache lines of its scattered writes
+// stay in one L2.  Inside a queue, the first rmin tiles of its blocks are
+// interleaved (id = lt * nblocks + jx) so that the tiles in flight belong to
+// many blocks and every look-back chain stays short; the remaining tiles
+// follow block by block.
+struct TileQueue {
+  u32 x, nq, nb, rmin;       // queue, queue count, blocks in queue, min tiles
+  const u32* rem_prefix;     // indexed by global large index x + nq * jx
+  __device__ inline u32 rem(u32 jx) const { return rem_prefix[x + nq * jx]; }
+  __device__ inline void locate(u32 id, u32& jx, u32& lt) const {
+    const u32 head = nb * rmin;
     if (id < head) {
-      j = id % nlarge;
-      lt = id / nlarge;
+      jx = id % nb;
+      lt = id / nb;
     } else {
-      const u32 x = id - head;
-      j = find_seg(rem_prefix, nlarge, x);
-      lt = rmin + (x - rem_prefix[j]);
+      const u32 y = id - head;
+      u32 lo = 0, hi = nb;
+      while (hi - lo > 1) {
+        const u32 mid = (lo + hi) >> 1;
+        if (rem(mid) <= y) lo = mid; else hi = mid;
+      }
+      jx = lo;
+      lt = rmin + (y - rem(jx));
     }
   }
-  __device__ inline u32 id_of(u32 j, u32 lt) const {
-    return lt < rmin ? lt * nlarge + j : nlarge * rmin + rem_prefix[j] + (lt - rmin);
+  __device__ inline u32 id_of(u32 jx, u32 lt) const {
+    return lt < rmin ? lt * nb + jx : nb * rmin + rem(jx) + (lt - rmin);
   }
 };
 

@@ -14,7 +14,9 @@ from dataclasses import dataclass
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "liblbsort.so")
+# LBSORT_LIB may point at another build of the same library (e.g. a variant
+# compiled for comparison); by default the in-tree build is used.
+LIB_PATH = os.environ.get("LBSORT_LIB") or os.path.join(HERE, "_lib", "liblbsort.so")
 
 U32, U64 = 1, 2
 NOVAL, VAL_U32 = 0, 1
