@@ -92,16 +92,123 @@ def cpu_baseline(w, sample_n):
                       f"{dt:.2f} s"}
 
 
+def bench_batch(args):
+    """Batched form: B uneven u32 key/value instances (sizes log-uniform in
+    [1K, 4M], uniform / normal / sorted / reverse keys), P = 8, sorted by one
+    lbsort_sort_batch call replayed from a HIP graph, against a loop of B
+    lbsort_sort_pairs calls over the same instances on the same stream."""
+    import numpy as np
+    import torch
+    from paper_1611_00463_amd import datagen
+    from paper_1611_00463_amd import lbsort as L
+    lib = L.load()
+    B, P = args.batch, 8
+    print(f"[bench] generating a batch of {B} instances", file=sys.stderr, flush=True)
+    keys, vals, seg, sizes = datagen.batch_u32_torch(B, 4, device="cuda")
+    total = int(sizes.sum())
+    plan = L.BatchPlan(keys, seg, P, vals=vals)
+    for _ in range(args.warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    plan.check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1) / args.steps
+    plan.capture()
+    for _ in range(args.warmup):
+        plan.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        plan.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / args.steps
+    plan.check()
+    # check, in chunks: every instance sorted and a permutation of its input
+    seg64 = seg.view(torch.int64)
+    CH = 1 << 27
+    for a in range(0, total, CH):
+        e = min(total, a + CH)
+        idx = torch.arange(a, e, device="cuda", dtype=torch.int64)
+        seg_of = torch.searchsorted(seg64, idx, right=True) - 1
+        ko = plan.keys_out[a:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        vo = plan.vals_out[a:e].view(torch.int32).to(torch.int64)
+        src = seg64[seg_of] + vo
+        ki = keys.view(torch.int32)[src].to(torch.int64) & 0xFFFFFFFF
+        assert bool((ki == ko).all()), "batched output is not a permutation of its instances"
+        same = seg_of[1:] == seg_of[:-1]
+        assert bool((ko[1:][same] >= ko[:-1][same]).all()), "batched output not sorted within instances"
+        del idx, seg_of, ko, vo, src, ki, same
+    # the per-instance loop
+    kout = torch.empty_like(keys)
+    vout = torch.empty_like(vals)
+    prm = L.Params(P, 0, 0, 0, 0, 0)
+    offs = torch.empty((B, P + 1), dtype=torch.int64, device="cuda")
+    need = ctypes.c_size_t(0)
+    parts = L.Parts(offs.data_ptr(), 0, 0, 0, 0)
+    L._check(lib.lbsort_sort_pairs(L.U32, L.VAL_U32, None, None, None, None, int(sizes.max()), ctypes.byref(prm),
+                                   ctypes.byref(parts), None, ctypes.byref(need), None))
+    wsb = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    have = ctypes.c_size_t(need.value)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    hseg = seg.cpu().numpy().astype(np.int64)
+    kp, vp, kop, vop = keys.data_ptr(), vals.data_ptr(), kout.data_ptr(), vout.data_ptr()
+    part_ptrs = [L.Parts(offs.data_ptr() + b * (P + 1) * 8, 0, 0, 0, 0) for b in range(B)]
+
+    def loop():
+        for b in range(B):
+            a, n = int(hseg[b]), int(hseg[b + 1] - hseg[b])
+            rc = lib.lbsort_sort_pairs(L.U32, L.VAL_U32, ctypes.c_void_p(kp + 4 * a), ctypes.c_void_p(vp + 4 * a),
+                                       ctypes.c_void_p(kop + 4 * a), ctypes.c_void_p(vop + 4 * a), n,
+                                       ctypes.byref(prm), ctypes.byref(part_ptrs[b]),
+                                       ctypes.c_void_p(wsb.data_ptr()), ctypes.byref(have), stream)
+            if rc:
+                L._check(rc)
+
+    loop()
+    torch.cuda.synchronize()
+    loops = max(1, args.steps // 5)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(loops):
+        loop()
+    e1.record()
+    torch.cuda.synchronize()
+    wall_loop = (time.perf_counter() - t0) * 1e3 / loops
+    ms_loop = e0.elapsed_time(e1) / loops
+    i32 = lambda t: t.view(torch.int32)
+    assert torch.equal(i32(kout), i32(plan.keys_out)) and torch.equal(i32(vout), i32(plan.vals_out)), \
+        "loop and batch differ"
+    line = {"metric": "batched sort: GKeys/s (u32 keys + u32 values), one graph launch vs a per-instance loop",
+            "value": round(total / (ms_graph / 1e3) / 1e9, 4), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_graph, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": f"batching: {B} uint32 key-value instances, sizes log-uniform in [1K, 4M], "
+                                   f"uniform/normal/sorted/reverse keys, P=8", "instances": B, "total_keys": total,
+                       "P": P},
+            "eager_ms": round(ms_eager, 4), "graph_ms": round(ms_graph, 4),
+            "loop_ms": round(ms_loop, 4), "loop_wall_ms": round(wall_loop, 2),
+            "loop_GKeys_s": round(total / (ms_loop / 1e3) / 1e9, 4),
+            "speedup_vs_loop": round(ms_loop / ms_graph, 3)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--fanin", type=int, default=0)
     ap.add_argument("--merge-tile", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=4096, help="instances for --workload batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (counter calibration)")
     args = ap.parse_args()
@@ -123,6 +230,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes": a.numel() * 8}))
         return
 
+    if args.workload == "batch":
+        return bench_batch(args)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -5,6 +5,7 @@
 // exchange and the merge use.  All of it is a few kilobytes of metadata;
 // nothing here touches the bulk of the data except the searches.
 #include "lbsort_internal.hpp"
+#include "select.hpp"
 
 namespace lbs {
 
@@ -67,6 +68,49 @@ __global__ __launch_bounds__(256) void k_splitters(Plan p) {
     v = ((const K*)p.pool)[a + (r < S - 1 ? r : S - 1)];
   }
   ((K*)p.splitters)[x] = v;
+}
+
+// Step 3 for P <= 16: splitter k is the element of rank t_k of the union of
+// the P sorted sample lists of its instance, found by the wave-wide
+// multi-sequence selection (one wave per splitter) without ranking every
+// sample: the element of rank t is the smallest first element beyond the split
+// of the first t elements.
+template <typename K, int F>
+__global__ __launch_bounds__(256) void k_select_splitters(Plan p) {
+  const u32 wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const u32 lane = threadIdx.x & 63;
+  const u32 per = p.P - 1;
+  if (wv >= p.B * per) return;
+  const u32 b = wv / per, k = wv % per + 1;
+  const u32 r = lane % F;
+  const u64 a0 = p.samp_start[b * p.P];
+  const u64 S = p.samp_start[(b + 1) * p.P] - a0;
+  K v = 0;
+  if (S > 0) {
+    const u64 t0 = ((u64)k * S) / p.P + p.P / 2 - 1;
+    const u64 t = t0 < S - 1 ? t0 : S - 1;
+    u64 roff = 0, rlen = 0;
+    if (r < p.P) {
+      roff = p.samp_start[b * p.P + r];
+      rlen = p.samp_start[b * p.P + r + 1] - roff;
+    }
+    const u64 lo = t + rlen > S ? t + rlen - S : 0;
+    const u64 hi = t < rlen ? t : rlen;
+    const K* smp = (const K*)p.samples;
+    const u64 cut = wave_select<K, F, F == 16 ? 8 : (F == 8 ? 4 : (F == 4 ? 2 : 1))>(smp, roff, lo, hi, t, p.counters);
+    // smallest key among the run fronts just past the split
+    bool has = cut < rlen;
+    K front = has ? smp[roff + cut] : (K)0;
+#pragma unroll
+    for (int o = 1; o < F; o <<= 1) {
+      const K of = __shfl_xor(front, o);
+      const bool oh = __shfl_xor((int)has, o) != 0;
+      if (oh && (!has || of < front)) front = of;
+      has = has || oh;
+    }
+    v = front;
+  }
+  if (lane == 0) ((K*)p.splitters)[(u64)b * per + k - 1] = v;
 }
 
 // Step 4: lo = #keys < v_k and hi = #keys <= v_k in every sorted block.  The
@@ -191,6 +235,17 @@ void launch_split(const Plan& p, const K* sorted, u64 max_samples, const void* o
   if (p.P > 1 && max_samples > 0) {
     { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_samples<K>, dim3((u32)((max_samples + 255) / 256)), dim3(256), 0, s, p, sorted,
                        max_samples); prof_end(pe_, "samples", s); }
+  }
+  if (p.P > 1 && p.P <= 16) {
+    const u32 waves = p.B * (p.P - 1);
+    const dim3 grid((waves + 3) / 4);
+    const int pe_ = prof_begin(s);
+    if (p.P <= 2) hipLaunchKernelGGL((k_select_splitters<K, 2>), grid, dim3(256), 0, s, p);
+    else if (p.P <= 4) hipLaunchKernelGGL((k_select_splitters<K, 4>), grid, dim3(256), 0, s, p);
+    else if (p.P <= 8) hipLaunchKernelGGL((k_select_splitters<K, 8>), grid, dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_select_splitters<K, 16>), grid, dim3(256), 0, s, p);
+    prof_end(pe_, "select_splitters", s);
+  } else if (p.P > 16 && max_samples > 0) {
     const u32 G = p.P >= 64 ? 64 : (p.P >= 32 ? 32 : (p.P >= 16 ? 16 : (p.P >= 8 ? 8 : (p.P >= 4 ? 4 : 2))));
     const u64 threads = max_samples * G;
     const dim3 grid((u32)((threads + 255) / 256));
@@ -207,7 +262,7 @@ void launch_split(const Plan& p, const K* sorted, u64 max_samples, const void* o
   }
   if (p.P > 1) {
     const u32 ns = p.B * (p.P - 1);
-    { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_splitters<K>, dim3((ns + 255) / 256), dim3(256), 0, s, p); prof_end(pe_, "splitters", s); }
+    if (p.P > 16) { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_splitters<K>, dim3((ns + 255) / 256), dim3(256), 0, s, p); prof_end(pe_, "splitters", s); }
     const u64 nq = (u64)p.B * p.P * (p.P - 1) * 2;
     { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_search<K>, dim3((u32)((nq + 255) / 256)), dim3(256), 0, s, p, sorted); prof_end(pe_, "search", s); }
   }

@@ -225,3 +225,40 @@ def uniform_keys_torch(n: int, seed: int, device="cuda", chunk: int = 1 << 26):
 def index_values_torch(n: int, device="cuda"):
     import torch
     return torch.arange(n, dtype=torch.int64, device=device).to(torch.int32).view(torch.uint32)
+
+
+def batch_u32_torch(B: int, seed: int = 4, lo: int = 1024, hi: int = 4194304, device="cuda"):
+    """batch_u32 generated on the device: the same sizes and distribution ids;
+    uniform, sorted and reverse instances are bit-identical to batch_u32, normal
+    instances use the same formula in device float64 (last-bit rounding of the
+    transcendental functions may differ from the host)."""
+    import torch
+    sizes = batch_sizes(B, seed, lo, hi)
+    dists = batch_dist_ids(B, seed)
+    offs = np.zeros(B + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    total = int(offs[-1])
+    keys = torch.empty(total, dtype=torch.int64, device=device)
+    for b in range(B):
+        a, e = int(offs[b]), int(offs[b + 1])
+        n = e - a
+        sb = (seed * 1000003 + b * 7919 + 17) & 0xFFFFFFFFFFFFFFFF
+        d = int(dists[b])
+        if d == 1:
+            ua = _lsr(u64_torch(sb, 0, n, device).view(torch.int64), 11).double() * (1.0 / 9007199254740992.0)
+            ub = _lsr(u64_torch(sb + 0x5bd1e995, 0, n, device).view(torch.int64), 11).double() * (1.0 / 9007199254740992.0)
+            z = torch.sqrt(-2.0 * torch.log1p(-ua)) * torch.cos(2.0 * math.pi * ub)
+            k = torch.clamp(torch.round(2.0 ** 31 + 2.0 ** 29 * z), 0, 2 ** 32 - 1).to(torch.int64)
+        else:
+            k = _lsr(u64_torch(sb, 0, n, device).view(torch.int64), 32)
+            if d >= 2:
+                k = torch.sort(k).values
+                if d == 3:
+                    k = torch.flip(k, dims=[0])
+        keys[a:e] = k
+    keys32 = keys.to(torch.int32).view(torch.uint32)
+    del keys
+    local = torch.arange(total, dtype=torch.int64, device=device)
+    seg_of = torch.repeat_interleave(torch.arange(B, device=device), torch.from_numpy(sizes).to(device))
+    vals = (local - torch.from_numpy(offs[:-1]).to(device)[seg_of]).to(torch.int32).view(torch.uint32)
+    return keys32, vals, torch.from_numpy(offs.astype(np.uint64)).to(device), sizes

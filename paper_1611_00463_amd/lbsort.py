@@ -237,3 +237,59 @@ def autotune(key_type: int, val_type: int, n: int, B: int, P: int, cache_path: s
 
 def load_tuning(cache_path: str):
     _check(load().lbsort_load_tuning(cache_path.encode()))
+
+
+class BatchPlan:
+    """A batched sort of fixed shape (Section IV.C, several data sets at once):
+    device buffers, workspace and partition outputs are allocated once, so the
+    call can be repeated and captured into a HIP graph (torch.cuda.CUDAGraph
+    records the library's launches on the capturing stream).
+
+    keys/vals: device tensors holding every instance back to back;
+    seg_offsets: device tensor of B+1 offsets.  Outputs land in self.keys_out,
+    self.vals_out and self.part_offsets ([B, P+1], relative to each segment).
+    """
+
+    def __init__(self, keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torch.Tensor | None = None,
+                 s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0,
+                 keys_out=None, vals_out=None):
+        lib = load()
+        self.keys, self.vals, self.seg = keys, vals, seg_offsets
+        self.B = seg_offsets.numel() - 1
+        self.P = P
+        self.keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+        self.vals_out = (torch.empty_like(vals) if vals_out is None else vals_out) if vals is not None else None
+        (self._parts, self.part_offsets, self.part_counts, self.splitters, _, _) = _alloc_parts(
+            self.B, P, keys.dtype, keys.device, False, False)
+        self._prm = _params(P, s, investigator, fanin, merge_tile)
+        self._args = (key_code(keys.dtype), VAL_U32 if vals is not None else NOVAL, _ptr(keys), _ptr(vals),
+                      _ptr(self.keys_out), _ptr(self.vals_out), _ptr(seg_offsets), self.B, keys.numel(),
+                      ctypes.byref(self._prm), ctypes.byref(self._parts))
+        need = ctypes.c_size_t(0)
+        _check(lib.lbsort_sort_batch(*self._args, None, ctypes.byref(need), None))
+        self.workspace = torch.empty(max(need.value, 256), dtype=torch.uint8, device=keys.device)
+        self._have = ctypes.c_size_t(self.workspace.numel())
+        self._ws = ctypes.c_void_p(self.workspace.data_ptr())
+        self.graph = None
+
+    def run(self):
+        """Enqueue the whole batched sort on the current stream."""
+        _check(load().lbsort_sort_batch(*self._args, self._ws, ctypes.byref(self._have), _stream()))
+
+    def capture(self):
+        """Record the sort into a HIP graph (one launch per replay)."""
+        self.run()                      # first run outside the capture (warm-up)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def check(self):
+        check(self.workspace)
