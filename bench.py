@@ -198,17 +198,63 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_serve(args):
+    """Served form: a Poisson stream of u64 sort requests (sizes log-uniform in
+    [10K, 64M], uniform / Zipf(1.2) / sorted / reverse keys sliced from 64M-key
+    device-resident pools), P = 64, continuous batching on 4 streams under a
+    64 GB HBM budget, against serving the same stream one request at a time."""
+    import torch
+    from paper_1611_00463_amd import datagen
+    from paper_1611_00463_amd import serve as S
+    pool_n = 1 << 26
+    print("[bench] generating request pools", file=sys.stderr, flush=True)
+    pools = [datagen.serve_pool_u64_torch(d, pool_n, 5, "cuda") for d in range(4)]
+    torch.cuda.synchronize()
+    srv = S.Server(pools, P=64, budget_bytes=64 << 30, streams=4)
+    warm = S.make_requests(64, seed=55, pool_n=pool_n, rate=args.serve_rate, lo=10_000, hi=pool_n)
+    srv.run(warm)
+    print(f"[bench] serving {args.serve_requests} requests at {args.serve_rate} req/s", file=sys.stderr, flush=True)
+    reqs = S.make_requests(args.serve_requests, seed=5, pool_n=pool_n, rate=args.serve_rate, lo=10_000, hi=pool_n)
+    t0 = time.perf_counter()
+    srv.run(reqs)
+    wall = time.perf_counter() - t0
+    served = S.summarize(reqs, wall)
+    offered = sum(r.n for r in reqs) / max(r.arrival for r in reqs) / 1e9
+    print("[bench] per-request baseline", file=sys.stderr, flush=True)
+    base = S.make_requests(args.serve_requests, seed=5, pool_n=pool_n, rate=args.serve_rate, lo=10_000, hi=pool_n)
+    S.run_per_request(pools, base[:8], 64)
+    base = S.make_requests(args.serve_requests, seed=5, pool_n=pool_n, rate=args.serve_rate, lo=10_000, hi=pool_n)
+    t0 = time.perf_counter()
+    S.run_per_request(pools, base, 64)
+    bwall = time.perf_counter() - t0
+    single = S.summarize(base, bwall)
+    line = {"metric": "served sort: delivered GKeys/s (u64) with p50/p99 latency, continuous batching vs "
+                      "one request at a time",
+            "value": served["GKeys_s"], "unit": "GKeys/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": round(wall * 1e3, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"serving: Poisson stream ({args.serve_rate:g} req/s) of {args.serve_requests} "
+                                   "u64 sort requests, sizes log-uniform in [10K, 64M], uniform/Zipf(1.2)/sorted/"
+                                   "reverse, P=64, 64 GB HBM budget, 4 streams", "P": 64},
+            "offered_GKeys_s": round(offered, 4), "served": served, "one_at_a_time": single,
+            "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"],
+            "speedup_vs_one_at_a_time": round(served["GKeys_s"] / single["GKeys_s"], 3)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch"])
+    ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch", "serve"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--fanin", type=int, default=0)
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--batch", type=int, default=4096, help="instances for --workload batch")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="requests for --workload serve")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second (serve)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (counter calibration)")
     args = ap.parse_args()
@@ -232,6 +278,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

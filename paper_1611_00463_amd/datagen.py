@@ -262,3 +262,29 @@ def batch_u32_torch(B: int, seed: int = 4, lo: int = 1024, hi: int = 4194304, de
     seg_of = torch.repeat_interleave(torch.arange(B, device=device), torch.from_numpy(sizes).to(device))
     vals = (local - torch.from_numpy(offs[:-1]).to(device)[seg_of]).to(torch.int32).view(torch.uint32)
     return keys32, vals, torch.from_numpy(offs.astype(np.uint64)).to(device), sizes
+
+
+def u64_torch_at(seed: int, idx):
+    """u64(seed, idx) for an int64 index tensor, on idx's device."""
+    import torch
+    z = (idx + 1) * _i64(0x9E3779B97F4A7C15) + _i64(seed)
+    z = (z ^ _lsr(z, 30)) * _i64(0xBF58476D1CE4E5B9)
+    z = (z ^ _lsr(z, 27)) * _i64(0x94D049BB133111EB)
+    return (z ^ _lsr(z, 31)).view(torch.uint64)
+
+
+def serve_pool_u64_torch(dist: int, n: int, seed: int = 5, device="cuda"):
+    """serve_pool_u64 generated on the device (same definition)."""
+    import torch
+    s = seed * 101 + dist
+    if dist == 1:
+        cdf = torch.from_numpy(zipf_cdf(1000000, 1.2)).to(device)
+        u = _lsr(u64_torch(s, 0, n, device).view(torch.int64), 11).double() * (1.0 / 9007199254740992.0)
+        r = torch.clamp(torch.searchsorted(cdf, u, right=True) + 1, max=len(cdf))
+        return u64_torch_at(s + 7, r.to(torch.int64))
+    k = uniform_keys_torch(n, s, device)
+    if dist == 0:
+        return k
+    flip = -(1 << 63)
+    srt = (torch.sort(k.view(torch.int64) ^ flip).values ^ flip).view(torch.uint64)
+    return srt if dist == 2 else torch.flip(srt.view(torch.int64), dims=[0]).view(torch.uint64)
