@@ -178,33 +178,56 @@ __global__ __launch_bounds__(256) void k_partition(Plan p, Level L, const K* __r
 }
 
 // ----------------------------------------------------------------- merge tile
-// Sequential merge of outputs [q, qend) of the pair A = [a0, a1), B = [a1, b1)
-// (both sorted, ties to A) starting at diagonal q - a0.  The two candidates
-// stay in registers, so each output costs one LDS read of the side consumed.
-template <typename K, bool IDX>
-__device__ inline void merge_run(const K* ck, const uint16_t* ci, K* nk, uint16_t* ni, u32 a0, u32 a1, u32 b1,
-                                 u32 q, u32 qend) {
-  const u32 la = a1 - a0, lb = b1 - a1;
-  const u32 diag = q - a0;
-  u32 lo = diag > lb ? diag - lb : 0, hi = diag < la ? diag : la;
-  while (lo < hi) {
-    const u32 mid = (lo + hi) >> 1;
-    if (ck[a0 + mid] <= ck[a1 + diag - 1 - mid]) lo = mid + 1; else hi = mid;
-  }
-  u32 ia = a0 + lo, ib = a1 + diag - lo;
-  K ka = ia < a1 ? ck[ia] : (K)0, kb = ib < b1 ? ck[ib] : (K)0;
-  for (; q < qend; ++q) {
-    const bool takeA = ib >= b1 || (ia < a1 && ka <= kb);
-    if (takeA) {
-      nk[q] = ka;
-      if (IDX) ni[q] = ci[ia];
-      ++ia;
-      ka = ia < a1 ? ck[ia] : (K)0;
-    } else {
-      nk[q] = kb;
-      if (IDX) ni[q] = ci[ib];
-      ++ib;
-      kb = ib < b1 ? ck[ib] : (K)0;
+// LDS layout of the merge: element q lives at slot q + q / 8.  A thread merges
+// IT = 8 consecutive outputs, so without the pad slot the 64 lanes of a wave
+// would touch LDS at a stride of 8 elements and pile onto the same banks.
+__device__ inline u32 pad8(u32 q) { return q + (q >> 3); }
+
+// One thread's IT consecutive outputs [q0, q0 + IT) of a merge level where
+// lists of `w` segments are merged pairwise (A = [a0, a1), B = [a1, b1), ties to
+// A).  The outputs are produced into registers; a thread whose range runs past
+// the end of its pair starts over in the next pair (merge-path search again).
+template <typename K, bool IDX, int IT, int F>
+__device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* so, int w, u32 q0, u32 n,
+                                    K (&ok)[IT], uint16_t (&oi)[IT]) {
+  u32 a1 = 0, b1 = 0, ia = 0, ib = 0;
+  K ka = 0, kb = 0;
+  auto start = [&](u32 q) {
+    u32 j = 0;
+#pragma unroll
+    for (int x = 2 * w; x < F; x += 2 * w) j += (q >= so[x]) ? 1u : 0u;
+    const u32 a0 = so[2 * j * w];
+    a1 = so[min((u32)((2 * j + 1) * w), (u32)F)];
+    b1 = so[min((u32)((2 * j + 2) * w), (u32)F)];
+    const u32 la = a1 - a0, lb = b1 - a1, diag = q - a0;
+    u32 lo = diag > lb ? diag - lb : 0, hi = diag < la ? diag : la;
+    while (lo < hi) {
+      const u32 mid = (lo + hi) >> 1;
+      if (ck[pad8(a0 + mid)] <= ck[pad8(a1 + diag - 1 - mid)]) lo = mid + 1; else hi = mid;
+    }
+    ia = a0 + lo;
+    ib = a1 + diag - lo;
+    ka = ia < a1 ? ck[pad8(ia)] : (K)0;
+    kb = ib < b1 ? ck[pad8(ib)] : (K)0;
+  };
+  if (q0 < n) start(q0);
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const u32 q = q0 + i;
+    if (q < n) {
+      if (q == b1) start(q);
+      const bool takeA = ib >= b1 || (ia < a1 && ka <= kb);
+      if (takeA) {
+        ok[i] = ka;
+        if (IDX) oi[i] = ci[pad8(ia)];
+        ++ia;
+        ka = ia < a1 ? ck[pad8(ia)] : (K)0;
+      } else {
+        ok[i] = kb;
+        if (IDX) oi[i] = ci[pad8(ib)];
+        ++ib;
+        kb = ib < b1 ? ck[pad8(ib)] : (K)0;
+      }
     }
   }
 }
@@ -213,9 +236,9 @@ template <typename K, bool HASV, int F, int TM>
 __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restrict__ src,
                                                const u32* __restrict__ srcv, K* __restrict__ dst,
                                                u32* __restrict__ dstv) {
-  constexpr int NT = 256, IT = TM / NT;
-  __shared__ K s_k[2][TM];
-  __shared__ uint16_t s_i[HASV ? 2 : 1][HASV ? TM : 1];
+  constexpr int NT = 256, IT = TM / NT, TP = TM + TM / 8;
+  __shared__ K s_k[TP];
+  __shared__ uint16_t s_i[HASV ? TP : 1];
   __shared__ u32 s_v[HASV ? TM : 1];
   __shared__ u64 s_roff[F];
   __shared__ u32 s_so[F + 1];
@@ -247,39 +270,34 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
     for (u32 q = tid; q < n; q += NT) {
       while (r + 1 < (u32)F && q >= s_so[r + 1]) ++r;
       const u64 e = s_roff[r] + (q - s_so[r]);
-      s_k[0][q] = src[e];
+      s_k[pad8(q)] = src[e];
       if (HASV) {
-        s_i[0][q] = (uint16_t)q;
+        s_i[pad8(q)] = (uint16_t)q;
         s_v[q] = srcv[e];
       }
     }
   }
   __syncthreads();
-  int cur = 0;
+  const u32 q0 = tid * IT;
 #pragma unroll
   for (int w = 1; w < F; w <<= 1) {
-    u32 q = tid * IT;
-    const u32 qend = q + IT < n ? q + IT : n;
-    while (q < qend) {
-      // the pair of lists (each `w` segments long) that holds output q
-      u32 j = 0;
+    K ok[IT];
+    uint16_t oi[IT];
+    merge_thread<K, HASV, IT, F>(s_k, s_i, s_so, w, q0, n, ok, oi);
+    __syncthreads();
 #pragma unroll
-      for (int x = 2 * w; x < F; x += 2 * w) j += (q >= s_so[x]) ? 1u : 0u;
-      const u32 a0 = s_so[2 * j * w];
-      const u32 a1 = s_so[min((u32)((2 * j + 1) * w), (u32)F)];
-      const u32 b1 = s_so[min((u32)((2 * j + 2) * w), (u32)F)];
-      const u32 sub_end = qend < b1 ? qend : b1;
-      merge_run<K, HASV>(s_k[cur], s_i[HASV ? cur : 0], s_k[cur ^ 1], s_i[HASV ? cur ^ 1 : 0], a0, a1, b1, q,
-                         sub_end);
-      q = sub_end;
+    for (int i = 0; i < IT; ++i) {
+      if (q0 + i < n) {
+        s_k[pad8(q0 + i)] = ok[i];
+        if (HASV) s_i[pad8(q0 + i)] = oi[i];
+      }
     }
     __syncthreads();
-    cur ^= 1;
   }
   const u64 out = p.rec_out[tile];
   for (u32 q = tid; q < n; q += NT) {
-    dst[out + q] = s_k[cur][q];
-    if (HASV) dstv[out + q] = s_v[s_i[cur][q]];
+    dst[out + q] = s_k[pad8(q)];
+    if (HASV) dstv[out + q] = s_v[s_i[pad8(q)]];
   }
 }
 
