@@ -177,7 +177,7 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
     for (u32 i = 0; i < p.P; ++i) {
       const u64 n = (u64)(((unsigned __int128)(i + 1) * total_n) / p.P) - (u64)(((unsigned __int128)i * total_n) / p.P);
       if (n >= (1ull << 32)) return fail(LBSORT_ERR_UNSUPPORTED, "a block of 2^32 keys or more (raise P)");
-      if (n > (u64)SORT_TILE) {
+      if (n > (u64)SMALL_TILE) {
         sh.has_large = true;
         sh.max_tiles += (n + SORT_TILE - 1) / SORT_TILE;
       } else if (n > 0) {

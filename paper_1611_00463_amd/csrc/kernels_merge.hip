@@ -216,18 +216,18 @@ __device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* 
     const u32 q = q0 + i;
     if (q < n) {
       if (q == b1) start(q);
+      // branch-free step: emit the smaller front, reload only the side consumed
       const bool takeA = ib >= b1 || (ia < a1 && ka <= kb);
-      if (takeA) {
-        ok[i] = ka;
-        if (IDX) oi[i] = ci[pad8(ia)];
-        ++ia;
-        ka = ia < a1 ? ck[pad8(ia)] : (K)0;
-      } else {
-        ok[i] = kb;
-        if (IDX) oi[i] = ci[pad8(ib)];
-        ++ib;
-        kb = ib < b1 ? ck[pad8(ib)] : (K)0;
-      }
+      const u32 from = takeA ? ia : ib;
+      ok[i] = takeA ? ka : kb;
+      if (IDX) oi[i] = ci[pad8(from)];
+      ia += takeA ? 1u : 0u;
+      ib += takeA ? 0u : 1u;
+      const u32 nx = from + 1;
+      const bool more = nx < (takeA ? a1 : b1);
+      const K nv = more ? ck[pad8(nx)] : (K)0;
+      ka = takeA ? nv : ka;
+      kb = takeA ? kb : nv;
     }
   }
 }

@@ -82,9 +82,9 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
       }
       p.blk_start[idx] = bs;
     }
-    const u64 tiles = n > (u64)SORT_TILE ? (n + SORT_TILE - 1) / SORT_TILE : 0;
+    const u64 tiles = n > (u64)SMALL_TILE ? (n + SORT_TILE - 1) / SORT_TILE : 0;
     const u64 smp = n < (u64)p.s ? n : (u64)p.s;
-    const u64 small = (n > 0 && n <= (u64)SORT_TILE) ? 1 : 0;
+    const u64 small = (n > 0 && n <= (u64)SMALL_TILE) ? 1 : 0;
     u64 tot;
     u64 ex = block_exclusive_scan<1024>(tiles, s_w, tot);
     if (idx < p.NB) p.tstart[idx] = (u32)(carry_t + ex);
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
     const u64 rem = p.blk_start[blk + 1] - tbase;
     const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
 #pragma unroll 4
-    for (int j = 0; j < SORT_ITEMS; ++j) {
+    for (int j = 0; j < SORT_TILE / SORT_NT; ++j) {
       const u32 idx = j * SORT_NT + tid;
       const bool valid = idx < tile_n;
       const K key = valid ? src[tbase + idx] : (K)0;
@@ -280,12 +280,13 @@ __device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n,
 // hands workgroups to the XCDs round-robin), then helps the other queues.
 // A tile waits only for tiles of its own queue with smaller tickets, which
 // running workgroups hold, so the waits always end.
-template <typename K, bool HASV>
-__global__ __launch_bounds__(SORT_NT, HASV ? 3 : 4) void k_onesweep(Plan p, const K* __restrict__ src,
-                                                      const u32* __restrict__ srcv, K* __restrict__ dst,
-                                                      u32* __restrict__ dstv, u32 pass) {
-  constexpr int NWV = SORT_NT / 64, WI = 64 * SORT_ITEMS;
-  static_assert(SORT_NT == RADIX, "one thread per digit");
+template <typename K, bool HASV, int NT, int ITEMS, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restrict__ src,
+                                                 const u32* __restrict__ srcv, K* __restrict__ dst,
+                                                 u32* __restrict__ dstv, u32 pass) {
+  constexpr int NWV = NT / 64, WI = 64 * ITEMS;
+  static_assert(NT * ITEMS == SORT_TILE, "tiles of SORT_TILE keys");
+  static_assert(NT >= RADIX, "one thread per digit");
   // LDS kept under 40 KB so that four workgroups fit on a compute unit:
   // 16-bit per-wave digit counters (they end up holding the tile-local start
   // of each wave's run of a digit), 32-bit block-relative write bases, keys
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(SORT_NT, HASV ? 3 : 4) void k_onesweep(Plan p, cons
     while (true) {
       __syncthreads();
       if (tid == 0) s_ticket = atomicAdd(&p.counters[C_TICKET + nq * pass + x], 1u);
-      for (int i = tid; i < NWV * RADIX; i += SORT_NT) (&s_wc[0][0])[i] = 0;
+      for (int i = tid; i < NWV * RADIX; i += NT) (&s_wc[0][0])[i] = 0;
       __syncthreads();
       const u32 t = s_ticket;
       if (t >= qtiles) break;
@@ -322,10 +323,10 @@ __global__ __launch_bounds__(SORT_NT, HASV ? 3 : 4) void k_onesweep(Plan p, cons
       const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
       const u32 wbase = w * WI;
 
-      K keys[SORT_ITEMS];
-      u32 vals[HASV ? SORT_ITEMS : 1];
+      K keys[ITEMS];
+      u32 vals[HASV ? ITEMS : 1];
 #pragma unroll
-      for (int j = 0; j < SORT_ITEMS; ++j) {
+      for (int j = 0; j < ITEMS; ++j) {
         const u32 idx = wbase + j * 64 + lane;
         if (idx < tile_n) {
           keys[j] = src[tbase + idx];
@@ -335,30 +336,33 @@ __global__ __launch_bounds__(SORT_NT, HASV ? 3 : 4) void k_onesweep(Plan p, cons
           if (HASV) vals[j] = 0;
         }
       }
-      u32 rank[SORT_ITEMS];
+      u32 rank[ITEMS];
       {
-        u32 dig[SORT_ITEMS];
-        rank_items<K, SORT_ITEMS, uint16_t>(keys, wbase, tile_n, shift, s_wc[w], rank, dig);
+        u32 dig[ITEMS];
+        rank_items<K, ITEMS, uint16_t>(keys, wbase, tile_n, shift, s_wc[w], rank, dig);
       }
       __syncthreads();
 
       // Per-digit tile count; per-wave counters become exclusive wave prefixes.
+      const u32 d = tid < RADIX ? tid : 0;
       u32 tot = 0, wpre[NWV];
 #pragma unroll
       for (int v = 0; v < NWV; ++v) {
         wpre[v] = tot;
-        tot += s_wc[v][tid];
+        tot += s_wc[v][d];
       }
+      if (tid >= RADIX) tot = 0;
       // Decoupled look-back over the earlier tiles of this block, digit = tid.
-      u64* st = p.status + (u64)(qbase + t) * RADIX + tid;
+      u64* st = p.status + (u64)(qbase + t) * RADIX + d;
       u64 excl = 0;
-      if (lt == 0) {
+      if (tid >= RADIX) {
+      } else if (lt == 0) {
         st_release_agent(st, st_pack(epoch, ST_INC, tot));
       } else {
         st_release_agent(st, st_pack(epoch, ST_AGG, tot));
         u32 plt = lt - 1, spins = 0;
         while (true) {
-          const u64 v = ld_acquire_agent(p.status + (u64)(qbase + Q.id_of(jx, plt)) * RADIX + tid);
+          const u64 v = ld_acquire_agent(p.status + (u64)(qbase + Q.id_of(jx, plt)) * RADIX + d);
           if ((u32)(v >> 56) != epoch) {
             if (++spins > SPIN_LIMIT) {
               set_error(p.counters, E_SPIN);
@@ -374,19 +378,21 @@ __global__ __launch_bounds__(SORT_NT, HASV ? 3 : 4) void k_onesweep(Plan p, cons
         st_release_agent(st, st_pack(epoch, ST_INC, excl + tot));
       }
       u64 ttot;
-      const u32 lstart = (u32)block_exclusive_scan<SORT_NT>(tot, s_scan, ttot);
+      const u32 lstart = (u32)block_exclusive_scan<NT>(tot, s_scan, ttot);
+      if (tid < RADIX) {
 #pragma unroll
-      for (int v = 0; v < NWV; ++v) s_wc[v][tid] = (uint16_t)(lstart + wpre[v]);
-      s_gbase[tid] = (u32)(p.hist[((u64)blk * p.D + pass) * RADIX + tid] + excl - lstart);
+        for (int v = 0; v < NWV; ++v) s_wc[v][tid] = (uint16_t)(lstart + wpre[v]);
+        s_gbase[tid] = (u32)(p.hist[((u64)blk * p.D + pass) * RADIX + tid] + excl - lstart);
+      }
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < SORT_ITEMS; ++j) {
+      for (int j = 0; j < ITEMS; ++j) {
         rank[j] += s_wc[w][(u32)(keys[j] >> shift) & (RADIX - 1)];  // rank[] now holds the staged position
         if (wbase + j * 64 + lane < tile_n) s_stage[rank[j]] = keys[j];
       }
       __syncthreads();
       K* dblk = dst + bstart;
-      for (u32 i = tid; i < tile_n; i += SORT_NT) {
+      for (u32 i = tid; i < tile_n; i += NT) {
         const K k = s_stage[i];
         const u32 d = (u32)(k >> shift) & (RADIX - 1);
         dblk[s_gbase[d] + i] = k;
@@ -396,11 +402,11 @@ __global__ __launch_bounds__(SORT_NT, HASV ? 3 : 4) void k_onesweep(Plan p, cons
         __syncthreads();
         u32* sv = (u32*)s_stage;
 #pragma unroll
-        for (int j = 0; j < SORT_ITEMS; ++j)
+        for (int j = 0; j < ITEMS; ++j)
           if (wbase + j * 64 + lane < tile_n) sv[rank[j]] = vals[j];
         __syncthreads();
         u32* vblk = dstv + bstart;
-        for (u32 i = tid; i < tile_n; i += SORT_NT) vblk[s_gbase[s_dig[i]] + i] = sv[i];
+        for (u32 i = tid; i < tile_n; i += NT) vblk[s_gbase[s_dig[i]] + i] = sv[i];
       }
     }
   }
@@ -418,8 +424,8 @@ __global__ __launch_bounds__(SORT_NT) void k_small_sort(Plan p, const K* __restr
   __shared__ u32 s_wc[NWV][RADIX];
   __shared__ u32 s_lstart[RADIX];
   __shared__ u64 s_scan[NWV];
-  __shared__ K s_keys[SORT_TILE];
-  __shared__ u32 s_vals[HASV ? SORT_TILE : 1];
+  __shared__ K s_keys[SMALL_TILE];
+  __shared__ u32 s_vals[HASV ? SMALL_TILE : 1];
   const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (blockIdx.x >= p.counters[C_NSMALL]) return;
   const u32 blk = p.small_list[blockIdx.x];
@@ -503,9 +509,13 @@ template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s) {
   if (p.max_tiles == 0) return;
   // persistent grid: a few workgroups per compute unit, a multiple of the queue count
-  u32 grid = p.persist_wgs < p.max_tiles ? p.persist_wgs : p.max_tiles;
+  // Keys with values: 512 threads x 8 keys (more waves per tile, fewer
+  // registers); keys only: 256 threads x 16 keys with four waves per SIMD.
+  constexpr int NT = HASV ? SORT_TILE / 8 : SORT_TILE / 16;
+  u32 grid = p.persist_wgs * 256 / NT;
+  grid = grid < p.max_tiles ? grid : p.max_tiles;
   grid = (grid + p.nq - 1) / p.nq * p.nq;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV>), dim3(grid), dim3(SORT_NT), 0, s, p, src, srcv, dst, dstv,
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, HASV ? 1 : 4>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst, dstv,
                      pass); prof_end(pe_, "onesweep", s); }
 }
 

@@ -10,12 +10,18 @@ namespace lbs {
 typedef uint32_t u32;
 typedef uint64_t u64;
 
-// Radix sort geometry (step 1): 8-bit digits, tiles of NT threads x ITEMS keys.
+// Radix sort geometry (step 1): 8-bit digits.  Blocks of at most SMALL_TILE
+// keys are sorted whole in LDS (SORT_NT threads x SORT_ITEMS keys); larger
+// blocks are cut into radix tiles of SORT_TILE keys.
+#ifndef LBS_RADIX_TILE
+#define LBS_RADIX_TILE 8192
+#endif
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SORT_NT = 256;
 constexpr int SORT_ITEMS = 16;
-constexpr int SORT_TILE = SORT_NT * SORT_ITEMS;  // 4096 keys per tile
+constexpr int SMALL_TILE = SORT_NT * SORT_ITEMS;  // 4096 keys
+constexpr int SORT_TILE = LBS_RADIX_TILE;
 constexpr int WAVE = 64;
 
 // Look-back status word: [63:56] epoch (pass + 1), [55:54] flag, [53:0] count.
