@@ -158,8 +158,8 @@ __global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
 // block.  A workgroup covers HIST_TILES consecutive tiles (block-contiguous
 // numbering) and flushes its LDS counts to the block's global counts when the
 // block changes, so global atomics are few.  Equal keys inside a wave are
-// first merged (a few leader rounds) so that heavy duplicates do not
-// serialise on one LDS counter.
+// first merged (the wave's remembered hot key, then a few leader rounds) so
+// that heavy duplicates do not serialise on one LDS counter.
 constexpr u32 HIST_TILES = 16;
 
 template <typename K>
@@ -176,6 +176,8 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
   if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t_begin);
   __syncthreads();
   u32 blk = s_blk;
+  K hot = 0;
+  bool have_hot = false;
   for (u32 t = t_begin; t < t_end; ++t) {
     if (t >= p.tstart[blk + 1]) {
       // next block: flush the counts of this one
@@ -197,6 +199,18 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
       const bool valid = idx < tile_n;
       const K key = valid ? src[tbase + idx] : (K)0;
       bool done = !valid;
+      if (have_hot) {
+        // the wave's hot key (a value seen in many lanes before) first
+        const u64 hm = __ballot(valid && key == hot);
+        if (__popcll(hm) >= 2) {
+          if (lane == (u32)(__ffsll((unsigned long long)hm) - 1)) {
+            const u32 c = (u32)__popcll(hm);
+#pragma unroll
+            for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((hot >> (q * RADIX_BITS)) & (RADIX - 1))], c);
+          }
+          done = done || key == hot;
+        }
+      }
       for (int r = 0; r < 3; ++r) {
         const u64 act = __ballot(!done);
         if (act == 0) break;
@@ -205,6 +219,10 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
         const bool same = !done && key == lk;
         const u64 sm = __ballot(same);
         if (__popcll(sm) < 2) break;  // no duplicate of the leader: leave all to the bulk path
+        if (__popcll(sm) >= 8) {
+          hot = lk;
+          have_hot = true;
+        }
         if (lane == (u32)leader) {
           const u32 c = (u32)__popcll(sm);
 #pragma unroll
