@@ -78,7 +78,7 @@ struct Shape {
 };
 
 struct Layout {
-  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
+  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, tdesc, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
       splitters, mtile, rec_start, rec_end, rec_out, rec_n, slot_grp, grp_run, grp_out, tmpk, tmpv, seg, total;
 };
 
@@ -101,6 +101,7 @@ static Layout make_layout(const Shape& sh) {
   l.samp_start = take((NB + 1) * 8);
   l.hist = take(NB * sh.D * RADIX * 4);
   l.status = take(sh.max_tiles * RADIX * 8);
+  l.tdesc = take(sh.max_tiles * sizeof(TileDesc));
   l.samples = take(sh.max_samples * K);
   l.pool = take(sh.max_samples * K);
   l.lo = take(B * P * (P - 1) * 8);
@@ -221,6 +222,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.small_list = (u32*)(ws + lay.small_list);
   p.large_list = (u32*)(ws + lay.large_list);
   p.rem_prefix = (u32*)(ws + lay.rem_prefix);
+  p.tdesc = (TileDesc*)(ws + lay.tdesc);
   p.counters = (u32*)(ws + lay.counters);
   p.hist = (u32*)(ws + lay.hist);
   p.status = (u64*)(ws + lay.status);

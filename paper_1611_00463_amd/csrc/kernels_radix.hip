@@ -149,6 +149,30 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
   }
 }
 
+// Status slot g of the radix passes (queue x owns slots [qbase_x, qbase_x +
+// tiles_x), ticket order): its block, tile and key range.
+__global__ __launch_bounds__(256) void k_tile_desc(Plan p) {
+  const u32 g = blockIdx.x * 256 + threadIdx.x;
+  for (u32 x = 0; x < p.nq; ++x) {
+    const u32 qbase = p.counters[C_QPARAM + 4 * x + 2], qtiles = p.counters[C_QPARAM + 4 * x + 3];
+    if (g < qbase || g - qbase >= qtiles) continue;
+    const TileQueue Q{x, p.nq, p.counters[C_QPARAM + 4 * x], p.counters[C_QPARAM + 4 * x + 1], p.rem_prefix};
+    u32 jx, lt;
+    Q.locate(g - qbase, jx, lt);
+    const u32 blk = p.large_list[x + p.nq * jx];
+    TileDesc d;
+    d.bstart = p.blk_start[blk];
+    d.tbase = d.bstart + (u64)lt * SORT_TILE;
+    const u64 rem = p.blk_start[blk + 1] - d.tbase;
+    d.blk = blk;
+    d.lt = lt;
+    d.jx = jx;
+    d.tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+    p.tdesc[g] = d;
+    return;
+  }
+}
+
 __global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) a[i] = v;
 }
@@ -161,6 +185,7 @@ __global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
 // first merged (the wave's remembered hot key, then a few leader rounds) so
 // that heavy duplicates do not serialise on one LDS counter.
 constexpr u32 HIST_TILES = 16;
+constexpr int LOOKBACK = 4;  // predecessors read per look-back round
 
 template <typename K>
 __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ src) {
@@ -277,13 +302,20 @@ __device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n,
   for (int j = 0; j < ITEMS; ++j) {
     const bool valid = wbase + j * 64 + lane < tile_n;
     const u32 d = (u32)(keys[j] >> shift) & (RADIX - 1);
-    u64 m = __ballot(valid);
+    // Peers: lanes whose digit equals this lane's.  For every digit bit the
+    // lane's bit is spread to a full-word mask t (signed one-bit extract);
+    // t ^ ballot marks the lanes whose bit differs, one 32-bit half at a time,
+    // and the peers are the valid lanes marked by no bit.
+    const u64 vm = __ballot(valid);
+    u32 xlo = 0, xhi = 0;
 #pragma unroll
     for (int b = 0; b < RADIX_BITS; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const u64 bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
+      const u32 t = (u32)__builtin_amdgcn_sbfe((int)d, b, 1);
+      const u64 bb = __ballot(t != 0u);
+      xlo |= t ^ (u32)bb;
+      xhi |= t ^ (u32)(bb >> 32);
     }
+    const u64 m = ((u64)((u32)(vm >> 32) & ~xhi) << 32) | ((u32)vm & ~xlo);
     const u32 below = count_below(m);
     u32 base = 0;
     if (valid) base = wc[d];
@@ -305,17 +337,24 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
   constexpr int NWV = NT / 64, WI = 64 * ITEMS;
   static_assert(NT * ITEMS == SORT_TILE, "tiles of SORT_TILE keys");
   static_assert(NT >= RADIX, "one thread per digit");
-  // LDS kept under 40 KB so that four workgroups fit on a compute unit:
-  // 16-bit per-wave digit counters (they end up holding the tile-local start
-  // of each wave's run of a digit), 32-bit block-relative write bases, keys
-  // staged in s_stage and values in the same buffer afterwards, and s_dig
-  // holding each staged position's digit for the value write.
+  // LDS: 16-bit per-wave digit counters (they end up holding the tile-local
+  // start of each wave's run of a digit), 32-bit block-relative write bases,
+  // keys staged in s_stage and values in the same buffer afterwards, and s_dig
+  // holding each staged position's digit for the value write (about 81 KB for
+  // 64-bit keys with values: one workgroup per compute unit).
   __shared__ uint16_t s_wc[NWV][RADIX];
   __shared__ u32 s_gbase[RADIX];
   __shared__ u64 s_scan[NWV];
   __shared__ K s_stage[SORT_TILE];
   __shared__ uint8_t s_dig[HASV ? SORT_TILE : 1];
+  // The workgroup's current ticket and its tile.  Thread 0 fetches the next
+  // ticket and tile while the current one is processed, so that per tile only
+  // the key loads wait on memory.  A tile still waits only for tiles with
+  // smaller tickets: the smallest unfinished ticket is always one a running
+  // workgroup is processing (any ticket held ahead belongs to a workgroup
+  // whose current tile is smaller), so the waits always end.
   __shared__ u32 s_ticket;
+  __shared__ TileDesc s_td;
   const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const u32 shift = pass * RADIX_BITS;
   const u32 epoch = pass + 1;
@@ -325,20 +364,26 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
     const TileQueue Q{x, nq, p.counters[C_QPARAM + 4 * x], p.counters[C_QPARAM + 4 * x + 1], p.rem_prefix};
     const u32 qbase = p.counters[C_QPARAM + 4 * x + 2];
     const u32 qtiles = p.counters[C_QPARAM + 4 * x + 3];
+    u32* const ticket = &p.counters[C_TICKET + nq * pass + x];
+    __syncthreads();
+    if (tid == 0) {
+      const u32 t0 = atomicAdd(ticket, 1u);
+      s_ticket = t0;
+      if (t0 < qtiles) s_td = p.tdesc[qbase + t0];
+    }
     while (true) {
-      __syncthreads();
-      if (tid == 0) s_ticket = atomicAdd(&p.counters[C_TICKET + nq * pass + x], 1u);
       for (int i = tid; i < NWV * RADIX; i += NT) (&s_wc[0][0])[i] = 0;
       __syncthreads();
-      const u32 t = s_ticket;
+      // the tile's numbers are the same in every lane: keep them in scalars
+      const u32 t = __builtin_amdgcn_readfirstlane(s_ticket);
       if (t >= qtiles) break;
-      u32 jx, lt;
-      Q.locate(t, jx, lt);
-      const u32 blk = p.large_list[x + nq * jx];
-      const u64 bstart = p.blk_start[blk];
-      const u64 tbase = bstart + (u64)lt * SORT_TILE;
-      const u64 rem = p.blk_start[blk + 1] - tbase;
-      const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+      const u32 blk = __builtin_amdgcn_readfirstlane(s_td.blk), lt = __builtin_amdgcn_readfirstlane(s_td.lt);
+      const u32 jx = __builtin_amdgcn_readfirstlane(s_td.jx), tile_n = __builtin_amdgcn_readfirstlane(s_td.tile_n);
+      const u64 bstart = uniform_u64(s_td.bstart), tbase = uniform_u64(s_td.tbase);
+      u32 nt = 0;
+      if (tid == 0) nt = atomicAdd(ticket, 1u);
+      u32 hv = 0;
+      if (tid < RADIX) hv = p.hist[((u64)blk * p.D + pass) * RADIX + tid];
       const u32 wbase = w * WI;
 
       K keys[ITEMS];
@@ -359,48 +404,55 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
         u32 dig[ITEMS];
         rank_items<K, ITEMS, uint16_t>(keys, wbase, tile_n, shift, s_wc[w], rank, dig);
       }
+      // The next tile's record, read by wave 0 into wave-uniform scalars (a
+      // struct here would be placed in LDS, per-lane copies cost registers).
+      const u32 ntu = __builtin_amdgcn_readfirstlane(nt);
+      u64 nd_bstart = 0, nd_tbase = 0;
+      u32 nd_blk = 0, nd_lt = 0, nd_jx = 0, nd_n = 0;
+      if (__builtin_amdgcn_readfirstlane(w) == 0 && ntu < qtiles) {
+        const TileDesc* q = p.tdesc + qbase + ntu;
+        nd_bstart = q->bstart;
+        nd_tbase = q->tbase;
+        nd_blk = q->blk;
+        nd_lt = q->lt;
+        nd_jx = q->jx;
+        nd_n = q->tile_n;
+      }
       __syncthreads();
 
-      // Per-digit tile count; per-wave counters become exclusive wave prefixes.
+      // Per-digit tile count.
       const u32 d = tid < RADIX ? tid : 0;
-      u32 tot = 0, wpre[NWV];
+      u32 tot = 0;
 #pragma unroll
-      for (int v = 0; v < NWV; ++v) {
-        wpre[v] = tot;
-        tot += s_wc[v][d];
-      }
+      for (int v = 0; v < NWV; ++v) tot += s_wc[v][d];
       if (tid >= RADIX) tot = 0;
       // Decoupled look-back over the earlier tiles of this block, digit = tid.
+      // The tile's aggregate is published and the first LOOKBACK predecessors
+      // are requested at once; the tile-local scan and the staging of the keys
+      // run while those loads are in flight, and the walk over them (in
+      // registers) follows.  A look-back that ends inside the window costs
+      // one memory round trip, mostly hidden.
       u64* st = p.status + (u64)(qbase + t) * RADIX + d;
-      u64 excl = 0;
-      if (tid >= RADIX) {
-      } else if (lt == 0) {
-        st_release_agent(st, st_pack(epoch, ST_INC, tot));
-      } else {
-        st_release_agent(st, st_pack(epoch, ST_AGG, tot));
-        u32 plt = lt - 1, spins = 0;
-        while (true) {
-          const u64 v = ld_acquire_agent(p.status + (u64)(qbase + Q.id_of(jx, plt)) * RADIX + d);
-          if ((u32)(v >> 56) != epoch) {
-            if (++spins > SPIN_LIMIT) {
-              set_error(p.counters, E_SPIN);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          excl += v & ST_VALMASK;
-          if (((v >> 54) & 3u) == ST_INC || plt == 0) break;
-          --plt;
-        }
-        st_release_agent(st, st_pack(epoch, ST_INC, excl + tot));
+      const bool lookback = tid < RADIX && lt > 0;
+      u32 plt = lt - 1;  // next predecessor to add
+      u64 v[LOOKBACK];
+      if (tid < RADIX) st_release_agent(st, st_pack(epoch, lt == 0 ? ST_INC : ST_AGG, tot));
+      if (lookback) {
+#pragma unroll
+        for (int i = 0; i < LOOKBACK; ++i)
+          v[i] = (u32)i <= plt ? ld_acquire_agent(p.status + (u64)(qbase + Q.id_of(jx, plt - i)) * RADIX + d) : 0;
       }
       u64 ttot;
       const u32 lstart = (u32)block_exclusive_scan<NT>(tot, s_scan, ttot);
       if (tid < RADIX) {
+        // per-wave counts become each wave's tile-local start of the digit
+        u32 run = lstart;
 #pragma unroll
-        for (int v = 0; v < NWV; ++v) s_wc[v][tid] = (uint16_t)(lstart + wpre[v]);
-        s_gbase[tid] = (u32)(p.hist[((u64)blk * p.D + pass) * RADIX + tid] + excl - lstart);
+        for (int wv = 0; wv < NWV; ++wv) {
+          const u32 c = s_wc[wv][tid];
+          s_wc[wv][tid] = (uint16_t)run;
+          run += c;
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -408,6 +460,46 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
         rank[j] += s_wc[w][(u32)(keys[j] >> shift) & (RADIX - 1)];  // rank[] now holds the staged position
         if (wbase + j * 64 + lane < tile_n) s_stage[rank[j]] = keys[j];
       }
+      u64 excl = 0;
+      if (lookback) {
+        u32 spins = 0;
+        while (true) {
+          bool done = false;
+          u32 used = 0;
+#pragma unroll
+          for (int i = 0; i < LOOKBACK; ++i) {
+            if (done || used != (u32)i || (u32)i > plt || (u32)(v[i] >> 56) != epoch) continue;
+            excl += v[i] & ST_VALMASK;
+            used = i + 1;
+            done = ((v[i] >> 54) & 3u) == ST_INC || plt == (u32)i;
+          }
+          if (done) break;
+          plt -= used;
+          if (used == 0) {  // the next predecessor has not published yet
+            if (++spins > SPIN_LIMIT) {
+              set_error(p.counters, E_SPIN);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+#pragma unroll
+          for (int i = 0; i < LOOKBACK; ++i)
+            v[i] = (u32)i <= plt ? ld_acquire_agent(p.status + (u64)(qbase + Q.id_of(jx, plt - i)) * RADIX + d) : 0;
+        }
+        st_release_agent(st, st_pack(epoch, ST_INC, excl + tot));
+      }
+      // Every thread read this tile's s_ticket and s_td before the barrier
+      // after the ranking; the next tile's record has arrived by now.
+      if (tid == 0) {
+        s_ticket = ntu;
+        s_td.bstart = nd_bstart;
+        s_td.tbase = nd_tbase;
+        s_td.blk = nd_blk;
+        s_td.lt = nd_lt;
+        s_td.jx = nd_jx;
+        s_td.tile_n = nd_n;
+      }
+      if (tid < RADIX) s_gbase[tid] = (u32)(hv + excl - lstart);
       __syncthreads();
       K* dblk = dst + bstart;
       for (u32 i = tid; i < tile_n; i += NT) {
@@ -501,7 +593,14 @@ __global__ __launch_bounds__(SORT_NT) void k_small_sort(Plan p, const K* __restr
 }
 
 // ----------------------------------------------------------------- launchers
-void launch_plan(const Plan& p, hipStream_t s) { { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, p); prof_end(pe_, "plan", s); } }
+void launch_plan(const Plan& p, hipStream_t s) {
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, p); prof_end(pe_, "plan", s); }
+  if (p.max_tiles) {
+    const int pe_ = prof_begin(s);
+    hipLaunchKernelGGL(k_tile_desc, dim3((p.max_tiles + 255) / 256), dim3(256), 0, s, p);
+    prof_end(pe_, "tile_desc", s);
+  }
+}
 
 void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s) {
   if (n == 0) return;
@@ -526,14 +625,13 @@ void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32
 template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s) {
   if (p.max_tiles == 0) return;
-  // persistent grid: a few workgroups per compute unit, a multiple of the queue count
-  // Keys with values: 512 threads x 8 keys (more waves per tile, fewer
-  // registers); keys only: 256 threads x 16 keys with four waves per SIMD.
-  constexpr int NT = HASV ? SORT_TILE / 8 : SORT_TILE / 16;
+  // Persistent grid: one 1024-thread workgroup (8 keys per thread) per
+  // compute unit, a multiple of the queue count.
+  constexpr int NT = SORT_TILE / 8;
   u32 grid = p.persist_wgs * 256 / NT;
   grid = grid < p.max_tiles ? grid : p.max_tiles;
   grid = (grid + p.nq - 1) / p.nq * p.nq;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, HASV ? 1 : 4>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst, dstv,
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, 1>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst, dstv,
                      pass); prof_end(pe_, "onesweep", s); }
 }
 

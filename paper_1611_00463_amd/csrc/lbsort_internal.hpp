@@ -48,6 +48,17 @@ enum DevErr : u32 {
   E_RANGE = 8u         // an instance or block too large for 32-bit counters
 };
 
+// One radix tile of a queue, resolved once per call (the mapping from a
+// queue's tickets to blocks and tiles is the same in every digit pass).
+struct TileDesc {
+  u64 bstart;  // first key of the tile's block
+  u64 tbase;   // first key of the tile
+  u32 blk;     // block index
+  u32 lt;      // tile index inside the block
+  u32 jx;      // block index inside the queue
+  u32 tile_n;  // keys in the tile
+};
+
 // Everything a kernel needs to know about one call, passed by value.
 struct Plan {
   u32 B, P, NB;          // instances, processors, blocks = B * P
@@ -65,6 +76,7 @@ struct Plan {
   u32* small_list;       // [NB]
   u32* large_list;       // [NB] blocks larger than one tile, in block order
   u32* rem_prefix;       // [NB+1] over large blocks: prefix of (tiles - C_RMIN)
+  TileDesc* tdesc;       // [max_tiles] by status slot (queue base + ticket)
   u32* counters;         // [C_COUNT]
   u32* hist;             // [NB][D][256]
   u64* status;           // [max_tiles][256]
@@ -108,6 +120,11 @@ __device__ inline u32 lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builti
 // Number of set bits of `mask` in lanes below the calling lane.
 __device__ inline u32 count_below(u64 mask) {
   return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0));
+}
+
+// A value every lane of the wave holds, moved to scalar registers.
+__device__ inline u64 uniform_u64(u64 v) {
+  return ((u64)__builtin_amdgcn_readfirstlane((u32)(v >> 32)) << 32) | __builtin_amdgcn_readfirstlane((u32)v);
 }
 
 __device__ inline void set_error(u32* counters, u32 bits) { atomicOr(&counters[C_ERR], bits); }
