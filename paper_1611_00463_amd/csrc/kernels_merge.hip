@@ -305,7 +305,10 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
 template <typename K, bool HASV, int F, int TM>
 static void run_level(const Plan& p, const Level& L, const K* src, const u32* srcv, K* dst, u32* dstv,
                       u64 max_tiles, hipStream_t s) {
-  constexpr int M = F == 2 ? 1 : (F == 4 ? 2 : (F == 8 ? 4 : 8));
+  // Fewest pivots that still give every run one per round: each round's
+  // pivots cost a binary search in every run, and with one wave per boundary
+  // the extra rounds are hidden by the many boundaries in flight.
+  constexpr int M = F * F / 64 > 1 ? F * F / 64 : 1;
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_merge_plan, dim3(1), dim3(1024), 0, s, p, L); prof_end(pe_, "merge_plan", s); }
   const u64 slots = max_tiles + L.NG + 1;
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M, false>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition_coarse", s); }
