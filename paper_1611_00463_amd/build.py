@@ -23,6 +23,9 @@ HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     # no packed FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a single lane takes the radix tile tickets: keep the atomic's result
+    # unwaited until it is used (the wave-combining rewrite waits at once)
+    "-Xarch_device", "-mllvm=-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -168,6 +168,8 @@ __global__ __launch_bounds__(256) void k_tile_desc(Plan p) {
     d.lt = lt;
     d.jx = jx;
     d.tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+    d.tail = Q.nb * Q.rmin + Q.rem(jx) - Q.rmin;
+    d.pad = 0;
     p.tdesc[g] = d;
     return;
   }
@@ -339,22 +341,33 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
   static_assert(NT >= RADIX, "one thread per digit");
   // LDS: 16-bit per-wave digit counters (they end up holding the tile-local
   // start of each wave's run of a digit), 32-bit block-relative write bases,
-  // keys staged in s_stage and values in the same buffer afterwards, and s_dig
-  // holding each staged position's digit for the value write (about 81 KB for
-  // 64-bit keys with values: one workgroup per compute unit).
-  __shared__ uint16_t s_wc[NWV][RADIX];
-  __shared__ u32 s_gbase[RADIX];
-  __shared__ u64 s_scan[NWV];
-  __shared__ K s_stage[SORT_TILE];
-  __shared__ uint8_t s_dig[HASV ? SORT_TILE : 1];
+  // and the tile staged in digit order: keys in s_stage, values in s_vstage,
+  // so both go out in one pass (about 105 KB for 64-bit keys with values: one
+  // workgroup per compute unit).  One struct, small fields first, so that
+  // they sit at addresses the LDS instructions' immediate offsets reach.
+  struct Smem {
+    u32 ticket;    // current ticket
+    TileDesc td;   // its tile
+    u64 scan[NWV];
+    u32 gbase[RADIX];
+    uint16_t wc[NWV][RADIX];
+    K stage[SORT_TILE];
+    u32 vstage[HASV ? SORT_TILE : 1];
+  };
+  __shared__ Smem sm;
+  auto& s_scan = sm.scan;
+  auto& s_gbase = sm.gbase;
+  auto& s_wc = sm.wc;
+  auto& s_stage = sm.stage;
+  auto& s_vstage = sm.vstage;
   // The workgroup's current ticket and its tile.  Thread 0 fetches the next
   // ticket and tile while the current one is processed, so that per tile only
   // the key loads wait on memory.  A tile still waits only for tiles with
   // smaller tickets: the smallest unfinished ticket is always one a running
   // workgroup is processing (any ticket held ahead belongs to a workgroup
   // whose current tile is smaller), so the waits always end.
-  __shared__ u32 s_ticket;
-  __shared__ TileDesc s_td;
+  auto& s_ticket = sm.ticket;
+  auto& s_td = sm.td;
   const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const u32 shift = pass * RADIX_BITS;
   const u32 epoch = pass + 1;
@@ -379,11 +392,16 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
       if (t >= qtiles) break;
       const u32 blk = __builtin_amdgcn_readfirstlane(s_td.blk), lt = __builtin_amdgcn_readfirstlane(s_td.lt);
       const u32 jx = __builtin_amdgcn_readfirstlane(s_td.jx), tile_n = __builtin_amdgcn_readfirstlane(s_td.tile_n);
+      const u32 tail = __builtin_amdgcn_readfirstlane(s_td.tail);
+      // status slot of tile u of this block, without memory accesses (the
+      // look-back requests its window at once)
+      auto slot_of = [&](u32 u) { return u < Q.rmin ? u * Q.nb + jx : tail + u; };
       const u64 bstart = uniform_u64(s_td.bstart), tbase = uniform_u64(s_td.tbase);
       u32 nt = 0;
       if (tid == 0) nt = atomicAdd(ticket, 1u);
       u32 hv = 0;
-      if (tid < RADIX) hv = p.hist[((u64)blk * p.D + pass) * RADIX + tid];
+      const u32* const hrow = p.hist + ((u64)blk * p.D + pass) * RADIX;
+      if (tid < RADIX) hv = hrow[tid];
       const u32 wbase = w * WI;
 
       K keys[ITEMS];
@@ -408,7 +426,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
       // struct here would be placed in LDS, per-lane copies cost registers).
       const u32 ntu = __builtin_amdgcn_readfirstlane(nt);
       u64 nd_bstart = 0, nd_tbase = 0;
-      u32 nd_blk = 0, nd_lt = 0, nd_jx = 0, nd_n = 0;
+      u32 nd_blk = 0, nd_lt = 0, nd_jx = 0, nd_n = 0, nd_tail = 0;
       if (__builtin_amdgcn_readfirstlane(w) == 0 && ntu < qtiles) {
         const TileDesc* q = p.tdesc + qbase + ntu;
         nd_bstart = q->bstart;
@@ -417,6 +435,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
         nd_lt = q->lt;
         nd_jx = q->jx;
         nd_n = q->tile_n;
+        nd_tail = q->tail;
       }
       __syncthreads();
 
@@ -440,7 +459,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
       if (lookback) {
 #pragma unroll
         for (int i = 0; i < LOOKBACK; ++i)
-          v[i] = (u32)i <= plt ? ld_acquire_agent(p.status + (u64)(qbase + Q.id_of(jx, plt - i)) * RADIX + d) : 0;
+          v[i] = (u32)i <= plt ? ld_acquire_agent(p.status + (u64)(qbase + slot_of(plt - i)) * RADIX + d) : 0;
       }
       u64 ttot;
       const u32 lstart = (u32)block_exclusive_scan<NT>(tot, s_scan, ttot);
@@ -458,7 +477,10 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         rank[j] += s_wc[w][(u32)(keys[j] >> shift) & (RADIX - 1)];  // rank[] now holds the staged position
-        if (wbase + j * 64 + lane < tile_n) s_stage[rank[j]] = keys[j];
+        if (wbase + j * 64 + lane < tile_n) {
+          s_stage[rank[j]] = keys[j];
+          if (HASV) s_vstage[rank[j]] = vals[j];
+        }
       }
       u64 excl = 0;
       if (lookback) {
@@ -484,7 +506,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
           }
 #pragma unroll
           for (int i = 0; i < LOOKBACK; ++i)
-            v[i] = (u32)i <= plt ? ld_acquire_agent(p.status + (u64)(qbase + Q.id_of(jx, plt - i)) * RADIX + d) : 0;
+            v[i] = (u32)i <= plt ? ld_acquire_agent(p.status + (u64)(qbase + slot_of(plt - i)) * RADIX + d) : 0;
         }
         st_release_agent(st, st_pack(epoch, ST_INC, excl + tot));
       }
@@ -498,25 +520,17 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
         s_td.lt = nd_lt;
         s_td.jx = nd_jx;
         s_td.tile_n = nd_n;
+        s_td.tail = nd_tail;
       }
       if (tid < RADIX) s_gbase[tid] = (u32)(hv + excl - lstart);
       __syncthreads();
-      K* dblk = dst + bstart;
+      K* const dblk = dst + bstart;
+      u32* const vblk = HASV ? dstv + bstart : nullptr;
       for (u32 i = tid; i < tile_n; i += NT) {
         const K k = s_stage[i];
-        const u32 d = (u32)(k >> shift) & (RADIX - 1);
-        dblk[s_gbase[d] + i] = k;
-        if (HASV) s_dig[i] = (uint8_t)d;
-      }
-      if (HASV) {
-        __syncthreads();
-        u32* sv = (u32*)s_stage;
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j)
-          if (wbase + j * 64 + lane < tile_n) sv[rank[j]] = vals[j];
-        __syncthreads();
-        u32* vblk = dstv + bstart;
-        for (u32 i = tid; i < tile_n; i += NT) vblk[s_gbase[s_dig[i]] + i] = sv[i];
+        const u32 o = s_gbase[(u32)(k >> shift) & (RADIX - 1)] + i;
+        dblk[o] = k;
+        if (HASV) vblk[o] = s_vstage[i];
       }
     }
   }

@@ -57,6 +57,8 @@ struct TileDesc {
   u32 lt;      // tile index inside the block
   u32 jx;      // block index inside the queue
   u32 tile_n;  // keys in the tile
+  u32 tail;    // ticket of the block's tile u >= rmin is tail + u (mod 2^32)
+  u32 pad;
 };
 
 // Everything a kernel needs to know about one call, passed by value.
