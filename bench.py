@@ -14,12 +14,19 @@ Measurement:
   with its algorithmic bytes per launch divided by its average launch time,
   both taken live from per-launch HIP events; the whole pipeline's fraction
   of the byte model (K+V)(2D+2)+K per key is reported beside it;
+* roofline.traffic: HBM bytes one launch of that kernel moved (FETCH_SIZE +
+  WRITE_SIZE, each scaled by what the same counter reads for a plain copy of
+  known size), read from the committed rocprofv3 summary of this workload
+  under profiles/; null when there is none or when the kernel's source file
+  has changed since the counters were taken;
 * cpu_baseline: the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
 import ctypes
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -29,16 +36,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = {"onesweep": "kernels_radix.hip", "merge": "kernels_merge.hip"}
 METRIC = "GKeys/s sorted (u64) + max/mean partition imbalance; batched vs per-instance"
 
 WORKLOADS = {
     "pairs": dict(desc="plain sort, key-value pairs: 268,435,456 uniform u64 keys, u32 payload = input index, "
-                       "P=64, 512 regular samples per block", n=1 << 28, P=64, s=512, vals=True, gen="uniform", seed=2),
+                       "P=64, 512 regular samples per block", n=1 << 28, P=64, s=512, vals=True, gen="uniform", seed=2,
+                  tag="pairs_2e28"),
     "dups": dict(desc="duplicate-heavy: 268,435,456 u64 keys, 50% one value and the rest Zipf(1.1) over 1,000 "
                       "values, P=64, 512 samples per block, keys only", n=1 << 28, P=64, s=512, vals=False,
-                 gen="dups", seed=3),
+                 gen="dups", seed=3, tag="dups_2e28"),
     "keys1m": dict(desc="plain sort: 1,048,576 uniform u64 keys, P=8, 16 regular samples per block, keys only",
-                   n=1 << 20, P=8, s=16, vals=False, gen="uniform", seed=1),
+                   n=1 << 20, P=8, s=16, vals=False, gen="uniform", seed=1, tag="keys1m"),
 }
 
 
@@ -48,6 +57,27 @@ def kernel_bytes_per_launch(name, n, kb, vb):
         return n * 2 * (kb + vb)          # read key+value, write key+value
     if name == "hist":
         return n * kb                     # read keys once for all digit counts
+    return None
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 summaries, or None if absent or taken on other kernel source."""
+    src = KERNEL_SOURCE.get(kernel)
+    if src is None:
+        return None
+    with open(os.path.join(ROOT, "paper_1611_00463_amd", "csrc", src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha256") == sha:
+                    return {"bytes": int(kv["fetch_bytes"]) + int(kv["write_bytes"]),
+                            "fetch_bytes": int(kv["fetch_bytes"]), "write_bytes": int(kv["write_bytes"]),
+                            "source": os.path.relpath(path, ROOT)}
     return None
 
 
@@ -331,9 +361,12 @@ def main():
     achieved = per_launch / (t / c / 1e3) / 1e9
     D = kb  # one 8-bit digit pass per key byte
     model_bytes = (kb + vb) * (2 * D + 2) + kb
+    tr = measured_traffic(dom, w["tag"])
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["bytes"] if tr else None,
             "bytes_per_launch": per_launch, "avg_launch_ms": round(t / c, 5)}
+    if tr:
+        roof["traffic_detail"] = tr
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
