@@ -223,9 +223,10 @@ __device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* 
       if (IDX) oi[i] = ci[pad8(from)];
       ia += takeA ? 1u : 0u;
       ib += takeA ? 0u : 1u;
-      const u32 nx = from + 1;
-      const bool more = nx < (takeA ? a1 : b1);
-      const K nv = more ? ck[pad8(nx)] : (K)0;
+      // the element after the consumed one; past the end of its segment it is
+      // never compared (the take test checks ia < a1 and ib < b1), and the
+      // array has slack slots so that the read stays inside it
+      const K nv = ck[pad8(from + 1)];
       ka = takeA ? nv : ka;
       kb = takeA ? kb : nv;
     }
@@ -236,7 +237,7 @@ template <typename K, bool HASV, int F, int TM>
 __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restrict__ src,
                                                const u32* __restrict__ srcv, K* __restrict__ dst,
                                                u32* __restrict__ dstv) {
-  constexpr int NT = 256, IT = TM / NT, TP = TM + TM / 8;
+  constexpr int NT = 256, IT = TM / NT, TP = TM + TM / 8 + 8;  // 8 slack slots past pad8(TM - 1)
   __shared__ K s_k[TP];
   __shared__ uint16_t s_i[HASV ? TP : 1];
   __shared__ u32 s_v[HASV ? TM : 1];
@@ -285,11 +286,15 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
     uint16_t oi[IT];
     merge_thread<K, HASV, IT, F>(s_k, s_i, s_so, w, q0, n, ok, oi);
     __syncthreads();
+    // q0 is a multiple of IT (4, 8 or 16) and (q0 mod 8) + i < 8 whenever
+    // i < 8, so pad8(q0 + i) = pad8(q0) + i + i / 8
+    static_assert(IT == 4 || IT == 8 || IT == 16, "outputs per thread");
+    const u32 pq = pad8(q0);
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       if (q0 + i < n) {
-        s_k[pad8(q0 + i)] = ok[i];
-        if (HASV) s_i[pad8(q0 + i)] = oi[i];
+        s_k[pq + i + (i >> 3)] = ok[i];
+        if (HASV) s_i[pq + i + (i >> 3)] = oi[i];
       }
     }
     __syncthreads();

@@ -181,24 +181,25 @@ __global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
 
 // ----------------------------------------------------------------- histogram
 // Digit counts of all passes for the tiles of large blocks, accumulated per
-// block.  A workgroup covers HIST_TILES consecutive tiles (block-contiguous
-// numbering) and flushes its LDS counts to the block's global counts when the
-// block changes, so global atomics are few.  Equal keys inside a wave are
+// block.  A workgroup covers `tpw` consecutive tiles (block-contiguous
+// numbering; at most HIST_TILES, fewer when there are few tiles so that the
+// grid still covers the chip) and flushes its LDS counts to the block's global
+// counts when the block changes, so global atomics are few.  Equal keys inside a wave are
 // first merged (the wave's remembered hot key, then a few leader rounds) so
 // that heavy duplicates do not serialise on one LDS counter.
 constexpr u32 HIST_TILES = 16;
 constexpr int LOOKBACK = 4;  // predecessors read per look-back round
 
 template <typename K>
-__global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ src) {
+__global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ src, u32 tpw) {
   constexpr int D = KeyT<K>::BITS / RADIX_BITS;
   __shared__ u32 h[D * RADIX];
   __shared__ u32 s_blk;
   const u32 tid = threadIdx.x, lane = tid & 63;
   const u32 total = p.tstart[p.NB];
-  const u32 t_begin = blockIdx.x * HIST_TILES;
+  const u32 t_begin = blockIdx.x * tpw;
   if (t_begin >= total) return;
-  const u32 t_end = t_begin + HIST_TILES < total ? t_begin + HIST_TILES : total;
+  const u32 t_end = t_begin + tpw < total ? t_begin + tpw : total;
   for (int i = tid; i < D * RADIX; i += SORT_NT) h[i] = 0;
   if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t_begin);
   __syncthreads();
@@ -626,7 +627,10 @@ void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s) {
 template <typename K>
 void launch_hist(const Plan& p, const K* src, hipStream_t s) {
   if (p.max_tiles == 0) return;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_hist<K>, dim3((p.max_tiles + HIST_TILES - 1) / HIST_TILES), dim3(SORT_NT), 0, s, p, src); prof_end(pe_, "hist", s); }
+  // tiles per workgroup: up to HIST_TILES, but at least a few workgroups per compute unit
+  u32 tpw = p.max_tiles / p.persist_wgs;
+  tpw = tpw < 1 ? 1 : (tpw > HIST_TILES ? HIST_TILES : tpw);
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_hist<K>, dim3((p.max_tiles + tpw - 1) / tpw), dim3(SORT_NT), 0, s, p, src, tpw); prof_end(pe_, "hist", s); }
   const u32 waves = p.NB * p.D;
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_scan_hist, dim3((waves + 3) / 4), dim3(256), 0, s, p); prof_end(pe_, "scan_hist", s); }
 }
