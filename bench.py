@@ -228,6 +228,79 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_balance(args):
+    """Balance study (Section V: Table 2 and the sample-size figures) at the
+    paper's size: N keys (10^9 by default) of each of the four input
+    distributions, sorted by P = 10 virtual processors with the sample budget
+    X = 256 KB / P and with 0.004X ... 1.4X, under each investigator mode at X.
+    Also min/max partition sizes for P = 8 ... 52 at 0.004X, X and 1.4X on
+    uniform keys.  value = the largest max/mean share over the four
+    distributions at X with the count-based investigator (Table 2's setting)."""
+    import numpy as np
+    import torch
+    from paper_1611_00463_amd import datagen
+    from paper_1611_00463_amd import lbsort as L
+    n, P = args.balance_n, 10
+    factors = (0.004, 0.04, 0.4, 1.0, 1.004, 1.04, 1.4)
+    modes = {"COUNT": L.INV_COUNT, "NONE": L.INV_NONE, "PAPER": L.INV_PAPER}
+    ws = L.Workspace("cuda")
+    kout = torch.empty(n, dtype=torch.uint64, device="cuda")
+
+    def shares(keys, P, s, mode):
+        r = L.sort_keys(keys, P, s=s, investigator=mode, keys_out=kout, workspace=ws)
+        L.check(ws.buf)
+        c = r.part_counts.view(torch.int64).cpu().numpy()[0].astype(np.float64)
+        return c
+
+    def summary(c):
+        return {"max_over_mean": round(float(c.max() / c.mean()), 6), "min_pct": round(float(100 * c.min() / c.sum()), 4),
+                "max_pct": round(float(100 * c.max() / c.sum()), 4), "max_minus_min": int(c.max() - c.min())}
+
+    table2, sweep, modes_at_x, rates = {}, {}, {}, {}
+    X = 262144 // (P * 8)
+    for dist in datagen.BALANCE_DISTS:
+        print(f"[bench] balance: {dist}", file=sys.stderr, flush=True)
+        keys = datagen.balance_keys_torch(dist, n, device="cuda")
+        torch.cuda.synchronize()
+        sweep[dist] = {}
+        for f in factors:
+            s = max(1, int(f * X))
+            sweep[dist][f"{f}X"] = dict(s=s, **summary(shares(keys, P, s, L.INV_COUNT)))
+        c = shares(keys, P, X, L.INV_COUNT)
+        table2[dist] = [round(float(100 * v / c.sum()), 3) for v in c]
+        modes_at_x[dist] = {m: summary(shares(keys, P, X, code)) for m, code in modes.items()}
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            L.sort_keys(keys, P, s=X, keys_out=kout, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        rates[dist] = round(n / (e0.elapsed_time(e1) / 3 / 1e3) / 1e9, 3)
+        del keys
+    print("[bench] balance: processor sweep", file=sys.stderr, flush=True)
+    keys = datagen.balance_keys_torch("uniform", n, device="cuda")
+    procs = {}
+    for Pp in (8, 16, 32, 52):
+        Xp = 262144 // (Pp * 8)
+        procs[str(Pp)] = {f"{f}X": dict(s=max(1, int(f * Xp)), **summary(shares(keys, Pp, max(1, int(f * Xp)), L.INV_COUNT)))
+                          for f in (0.004, 1.0, 1.4)}
+        # X rounded down to a multiple of P: every splitter's target rank k*s/P is a whole sample
+        sm = max(Pp, Xp // Pp * Pp)
+        procs[str(Pp)]["X_multiple_of_P"] = dict(s=sm, **summary(shares(keys, Pp, sm, L.INV_COUNT)))
+    worst = max(modes_at_x[d]["COUNT"]["max_over_mean"] for d in datagen.BALANCE_DISTS)
+    line = {
+        "metric": "max/mean partition share, balance study (Table 2 setting)", "value": worst, "unit": "ratio",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": round(worst / 1.0022, 4), "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"balance study: {n:,} u64 keys per distribution (uniform, normal, right-skewed, "
+                               f"exponential), P=10, s = X = {X} and 0.004X..1.4X, COUNT/NONE/PAPER",
+                   "n": n, "P": P, "X": X},
+        "table2_shares_pct": table2, "sample_sweep": sweep, "modes_at_X": modes_at_x, "processor_sweep": procs,
+        "GKeys_s_at_X": rates,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_serve(args):
     """Served form: a Poisson stream of u64 sort requests (sizes log-uniform in
     [10K, 64M], uniform / Zipf(1.2) / sorted / reverse keys sliced from 64M-key
@@ -277,7 +350,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch", "serve"])
+    ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch", "serve", "balance"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--fanin", type=int, default=0)
@@ -285,6 +358,7 @@ def main():
     ap.add_argument("--batch", type=int, default=4096, help="instances for --workload batch")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests for --workload serve")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second (serve)")
+    ap.add_argument("--balance-n", type=int, default=1_000_000_000, help="keys per distribution (balance)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (counter calibration)")
     args = ap.parse_args()
@@ -310,6 +384,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "balance":
+        return bench_balance(args)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -78,7 +78,9 @@ extern "C" {
 typedef struct lbsort_params {
   uint32_t P;            /* virtual processors = output partitions, 1..LBSORT_MAX_P      */
   uint32_t s;            /* regular samples per block; 0 = the paper's budget: one 256 KB
-                            read buffer over all processors, max(1, 262144 / (P * key bytes)) */
+                            read buffer over all processors, b = 262144 / (P * key bytes),
+                            taken as the largest multiple of P not above b (b if b < P,
+                            at least 1)                                                     */
   uint32_t investigator; /* LBSORT_INV_*                                                     */
   uint32_t fanin;        /* handler merge fan-in F per pass: 0 = tuned, else 2, 4, 8 or 16   */
   uint32_t merge_tile;   /* elements per merge tile: 0 = tuned, else 1024, 2048 or 4096     */

@@ -47,9 +47,14 @@ READ_BUFFER_BYTES = 256 * 1024  # PGX.D read buffer (Section IV.B)
 
 
 def default_sample_count(P: int, key_bytes: int) -> int:
-    """Samples per processor so that all processors together send one 256 KB
-    read buffer to Master: 256/p KB each (Section IV.B)."""
-    return max(1, READ_BUFFER_BYTES // (P * key_bytes))
+    """Samples per processor within the budget of Section IV.B: all processors
+    together send at most one 256 KB read buffer to Master, 256/p KB each.
+    Taken as the largest multiple of P samples within that budget (the budget
+    itself if it is below P): then every splitter's target rank k*s/P falls on
+    a whole sample, which keeps large, alike blocks from drifting by up to half
+    a sample interval per splitter."""
+    b = READ_BUFFER_BYTES // (P * key_bytes)
+    return b // P * P if b >= P else max(1, b)
 
 
 def block_bounds(N: int, P: int) -> list[int]:

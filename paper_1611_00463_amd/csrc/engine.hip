@@ -155,7 +155,10 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   sh.local_only = local_only;
   const u32 kb = key_type == LBSORT_U64 ? 8 : 4;
   sh.D = kb * 8 / RADIX_BITS;
-  sh.s = p.s ? p.s : (262144u / (p.P * kb) > 0 ? 262144u / (p.P * kb) : 1u);
+  // default budget: the largest multiple of P samples within one 256 KB read
+  // buffer over all processors (that budget itself when it is below P)
+  const u32 budget = 262144u / (p.P * kb);
+  sh.s = p.s ? p.s : (budget >= p.P ? budget / p.P * p.P : (budget > 0 ? budget : 1u));
   // merge fan-in and tile: explicit, else tuned, else defaults
   Tuned tu = tuning_lookup(key_type, val_type, total_n / B, B, p.P);
   u32 F = p.fanin ? p.fanin : tu.fanin;

@@ -189,6 +189,53 @@ def serve_pool_u64(dist: int, n: int, seed: int = 5) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Stand-ins for the four input distributions of Section V (uniform, normal,
+# right-skewed, exponential; Table 2 and the sample-size study).  The paper
+# gives no parameters, so these are chosen here, and built from integer
+# operations only, so that the host and the device draw the same bytes:
+#   uniform      U64
+#   normal       Irwin-Hall: the sum of four independent 62-bit uniforms
+#                (bell-shaped around 2^63)
+#   right_skewed (U >> 43)^3 >> 47: a 21-bit uniform cubed and cut to 16 bits,
+#                mass near zero and a long right tail, many repeated keys
+#   exponential  the number of leading zero bits of a uniform u64: a discrete
+#                exponential (geometric) law, P(k) = 2^-(k+1), so half of the
+#                keys share one value
+# --------------------------------------------------------------------------
+BALANCE_DISTS = ("uniform", "normal", "right_skewed", "exponential")
+
+
+def _clz64(x: np.ndarray) -> np.ndarray:
+    k = np.zeros(x.shape, dtype=np.uint64)
+    y = x.copy()
+    for sh in (32, 16, 8, 4, 2, 1):
+        m = (y >> np.uint64(64 - sh)) == 0
+        k[m] += np.uint64(sh)
+        y[m] <<= np.uint64(sh)
+    k[x == 0] = np.uint64(64)
+    return k
+
+
+def balance_keys(dist: str, n: int, seed: int = 6, start: int = 0) -> np.ndarray:
+    """u64 keys [start, start + n) of one of BALANCE_DISTS."""
+    i = np.arange(start, start + n, dtype=np.uint64)
+    if dist == "uniform":
+        return u64(seed, i)
+    if dist == "normal":
+        acc = np.zeros(n, dtype=np.uint64)
+        for j in range(4):
+            acc += u64(seed + 1000 * (j + 1), i) >> np.uint64(2)
+        return acc
+    if dist == "right_skewed":
+        u = u64(seed, i) >> np.uint64(43)
+        with np.errstate(over="ignore"):
+            return (u * u * u) >> np.uint64(47)
+    if dist == "exponential":
+        return _clz64(u64(seed, i))
+    raise ValueError(dist)
+
+
+# --------------------------------------------------------------------------
 # The same streams generated on the device with torch int64 arithmetic
 # (wrapping multiply, logical shifts by masking); bit-identical to u64().
 # --------------------------------------------------------------------------
@@ -288,3 +335,37 @@ def serve_pool_u64_torch(dist: int, n: int, seed: int = 5, device="cuda"):
     flip = -(1 << 63)
     srt = (torch.sort(k.view(torch.int64) ^ flip).values ^ flip).view(torch.uint64)
     return srt if dist == 2 else torch.flip(srt.view(torch.int64), dims=[0]).view(torch.uint64)
+
+
+def _clz64_torch(x):
+    import torch
+    k = torch.zeros_like(x)
+    y = x.clone()
+    for sh in (32, 16, 8, 4, 2, 1):
+        m = _lsr(y, 64 - sh) == 0
+        k = torch.where(m, k + sh, k)
+        y = torch.where(m, y << sh, y)
+    return torch.where(x == 0, torch.full_like(x, 64), k)
+
+
+def balance_keys_torch(dist: str, n: int, seed: int = 6, device="cuda", chunk: int = 1 << 26):
+    """balance_keys(dist, n, seed) generated on the device (bit-identical)."""
+    import torch
+    out = torch.empty(n, dtype=torch.int64, device=device)
+    for a in range(0, n, chunk):
+        e = min(n, a + chunk)
+        if dist == "uniform":
+            v = u64_torch(seed, a, e - a, device).view(torch.int64)
+        elif dist == "normal":
+            v = torch.zeros(e - a, dtype=torch.int64, device=device)
+            for j in range(4):
+                v += _lsr(u64_torch(seed + 1000 * (j + 1), a, e - a, device).view(torch.int64), 2)
+        elif dist == "right_skewed":
+            u = _lsr(u64_torch(seed, a, e - a, device).view(torch.int64), 43)
+            v = _lsr(u * u * u, 47)
+        elif dist == "exponential":
+            v = _clz64_torch(u64_torch(seed, a, e - a, device).view(torch.int64))
+        else:
+            raise ValueError(dist)
+        out[a:e] = v
+    return out.view(torch.uint64)

@@ -237,11 +237,17 @@ def test_special_cases():
 
 
 def test_sample_budget_is_one_read_buffer():
-    """Section IV.B: each of p processors sends 256/p KB, one 256 KB buffer in all."""
+    """Section IV.B: each of p processors sends at most 256/p KB, one 256 KB
+    buffer in all; the count is the largest multiple of p within it."""
     assert O.default_sample_count(8, 8) == 4096
     assert O.default_sample_count(64, 8) == 512
-    assert O.default_sample_count(10, 8) == 3276
+    assert O.default_sample_count(10, 8) == 3270      # 3276 rounded down to a multiple of 10
+    assert O.default_sample_count(52, 8) == 624       # 630 -> 624
     assert O.default_sample_count(8, 4) == 8192
+    assert O.default_sample_count(1024, 8) == 32      # budget below P: the budget itself
+    for P in (3, 10, 52, 100, 1000):
+        s = O.default_sample_count(P, 8)
+        assert s * P * 8 <= 262144 and (s % P == 0 or s < P)
 
 
 # ------------------------------------------------------------------ the handler
