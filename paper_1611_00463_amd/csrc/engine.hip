@@ -2,6 +2,7 @@
 // sequence of one call (steps 1-6 of Section IV), all enqueued on the
 // caller's stream with no host synchronisation in between.
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -22,6 +23,8 @@ template <typename K, bool HASV>
 void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s);
 template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s);
+template <bool HASV>
+void launch_group_fix(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s);
 template <typename K>
 void launch_split(const Plan& p, const K* sorted, u64 max_samples, const void* out_offsets, void* out_counts,
                   void* out_send, void* out_cuts, void* out_split, hipStream_t s);
@@ -51,6 +54,13 @@ __global__ void k_seg2(u64* seg, u64 n) {
 static inline u64 align256(u64 x) { return (x + 255) & ~(u64)255; }
 
 // Compute units of the current device (cached per device).
+// The local sort of 64-bit keys: top three digits plus the group fix-up
+// (default), or all eight radix passes when LBSORT_LOCAL_SORT=lsd.
+static bool hybrid_local_sort() {
+  const char* v = getenv("LBSORT_LOCAL_SORT");
+  return !(v && strcmp(v, "lsd") == 0);
+}
+
 static u32 device_cus() {
   static int cached_dev = -1;
   static u32 cached = 0;
@@ -78,7 +88,7 @@ struct Shape {
 };
 
 struct Layout {
-  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, tdesc, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
+  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, tdesc, gflags, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
       splitters, mtile, rec_start, rec_end, rec_out, rec_n, slot_grp, grp_run, grp_out, tmpk, tmpv, seg, total;
 };
 
@@ -102,6 +112,7 @@ static Layout make_layout(const Shape& sh) {
   l.hist = take(NB * sh.D * RADIX * 4);
   l.status = take(sh.max_tiles * RADIX * 8);
   l.tdesc = take(sh.max_tiles * sizeof(TileDesc));
+  l.gflags = take(NB * 4);
   l.samples = take(sh.max_samples * K);
   l.pool = take(sh.max_samples * K);
   l.lo = take(B * P * (P - 1) * 8);
@@ -226,6 +237,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.large_list = (u32*)(ws + lay.large_list);
   p.rem_prefix = (u32*)(ws + lay.rem_prefix);
   p.tdesc = (TileDesc*)(ws + lay.tdesc);
+  p.gflags = (u32*)(ws + lay.gflags);
   p.counters = (u32*)(ws + lay.counters);
   p.hist = (u32*)(ws + lay.hist);
   p.status = (u64*)(ws + lay.status);
@@ -269,9 +281,40 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   launch_plan(p, st);
   if (sh.has_large) launch_hist<K>(p, kin, st);
   if (sh.has_small) launch_small_sort<K, HASV>(p, kin, vin, dk(sh.D - 1), dv(sh.D - 1), st);
-  if (sh.has_large)
-    for (u32 j = 0; j < sh.D; ++j)
-      launch_onesweep<K, HASV>(p, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);
+  if (sh.has_large) {
+    if constexpr (sizeof(K) == 8) {
+      if (hybrid_local_sort()) {
+        // 64-bit keys: the three highest digits first (blocks grouped by their
+        // top 24 bits), then the group fix-up into the step-1 output F; the
+        // blocks it flags are sorted again over all eight digits.
+        K* const F = dk(sh.D - 1);
+        u32* const FV = dv(sh.D - 1);
+        K* const O = F == kout ? tk : kout;
+        u32* const OV = HASV ? (FV == vout ? tv : vout) : nullptr;
+        launch_fill32(p.gflags, p.NB, 0, st);
+        launch_onesweep<K, HASV>(p, kin, vin, O, OV, 5, st);
+        launch_onesweep<K, HASV>(p, O, OV, F, FV, 6, st);
+        launch_onesweep<K, HASV>(p, F, FV, O, OV, 7, st);
+        launch_group_fix<HASV>(p, (const u64*)O, OV, (u64*)F, FV, st);
+        Plan q = p;
+        q.only = p.gflags;
+        q.epoch_base = 8;  // the status words of the passes above stay valid for epochs 6..8
+        launch_fill32(p.counters + C_TICKET, NQ * sh.D, 0, st);
+        launch_plan(q, st);
+        launch_fill32(p.hist, (u64)p.NB * sh.D * RADIX, 0, st);
+        launch_hist<K>(q, kin, st);
+        for (u32 j = 0; j < sh.D; ++j)
+          launch_onesweep<K, HASV>(q, j ? (j % 2 ? O : F) : kin, j ? (j % 2 ? OV : FV) : vin, j % 2 ? F : O,
+                                   j % 2 ? FV : OV, j, st);
+      } else {
+        for (u32 j = 0; j < sh.D; ++j)
+          launch_onesweep<K, HASV>(p, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);
+      }
+    } else {
+      for (u32 j = 0; j < sh.D; ++j)
+        launch_onesweep<K, HASV>(p, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);
+    }
+  }
   if (!sh.local_only) {
     const K* sorted = dk(sh.D - 1);
     launch_split<K>(p, sorted, sh.max_samples, parts->part_offsets, parts->part_counts, parts->send_counts,

@@ -46,6 +46,40 @@ __device__ inline u64 block_exclusive_scan(u64 v, u64* s_w, u64& total) {
   return wprefix + x - v;
 }
 
+// Exclusive running extreme over the workgroup's threads of small signed
+// values: FROM_LEFT gives the max over threads < tid (identity -1), otherwise
+// the min over threads > tid (identity INT_MAX).
+template <int NT, bool FROM_LEFT>
+__device__ inline int block_exclusive_extreme(int v, int* s_w) {
+  constexpr int NWV = NT / 64;
+  constexpr int ID = FROM_LEFT ? -1 : 0x7FFFFFFF;
+  const u32 lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    if (FROM_LEFT) {
+      const int y = __shfl_up(x, o);
+      if (lane >= (u32)o) x = x > y ? x : y;
+    } else {
+      const int y = __shfl_down(x, o);
+      if (lane + o < 64) x = x < y ? x : y;
+    }
+  }
+  int ex = FROM_LEFT ? __shfl_up(x, 1) : __shfl_down(x, 1);
+  if (FROM_LEFT ? lane == 0 : lane == 63) ex = ID;
+  if (FROM_LEFT ? lane == 63 : lane == 0) s_w[w] = x;
+  __syncthreads();
+  int c = ID;
+  for (int q = 0; q < NWV; ++q) {
+    if (FROM_LEFT ? (u32)q < w : (u32)q > w) {
+      const int y = s_w[q];
+      c = FROM_LEFT ? (c > y ? c : y) : (c < y ? c : y);
+    }
+  }
+  __syncthreads();
+  return FROM_LEFT ? (c > ex ? c : ex) : (c < ex ? c : ex);
+}
+
 // ----------------------------------------------------------------- plan
 // One workgroup: block starts, radix tile prefix, list of blocks small enough
 // to be sorted whole in LDS, and sample offsets, for every block of every
@@ -82,9 +116,12 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
       }
       p.blk_start[idx] = bs;
     }
-    const u64 tiles = n > (u64)SMALL_TILE ? (n + SORT_TILE - 1) / SORT_TILE : 0;
+    // with a filter, only the listed large blocks are planned (small blocks
+    // and sample offsets are unaffected by it)
+    const bool keep = p.only == nullptr || (idx < p.NB && p.only[idx] != 0);
+    const u64 tiles = (keep && n > (u64)SMALL_TILE) ? (n + SORT_TILE - 1) / SORT_TILE : 0;
     const u64 smp = n < (u64)p.s ? n : (u64)p.s;
-    const u64 small = (n > 0 && n <= (u64)SMALL_TILE) ? 1 : 0;
+    const u64 small = (p.only == nullptr && n > 0 && n <= (u64)SMALL_TILE) ? 1 : 0;
     u64 tot;
     u64 ex = block_exclusive_scan<1024>(tiles, s_w, tot);
     if (idx < p.NB) p.tstart[idx] = (u32)(carry_t + ex);
@@ -371,7 +408,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
   auto& s_td = sm.td;
   const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const u32 shift = pass * RADIX_BITS;
-  const u32 epoch = pass + 1;
+  const u32 epoch = pass + 1 + p.epoch_base;
   const u32 nq = p.nq;
   for (u32 qi = 0; qi < nq; ++qi) {
     const u32 x = (blockIdx.x + qi) % nq;
@@ -536,6 +573,114 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
     }
   }
 }
+
+// ----------------------------------------------------------------- group fix-up
+// Second phase of the local sort of 64-bit keys.  The large blocks arrive
+// stably sorted by their top 24 bits (radix passes over the three highest
+// digits); a group is a run of keys with equal top bits, and each group must
+// end up sorted by the whole key, stably.  One workgroup per tile of a large
+// block, with a window of GF_HALO keys on either side in LDS:
+//  * a group of at most GF_HALO keys lies inside the window of every tile
+//    that holds one of its keys; each key's place is the group start plus
+//    the number of group members before it in (key, position) order;
+//  * a larger group keeps its order, which is right when all its keys are
+//    equal (heavy duplicates); a key of it that differs from its predecessor
+//    flags the block, which is then sorted again over all eight digits.
+constexpr u32 GF_HALO = 64;
+constexpr u32 GF_SHIFT = 40;
+constexpr int GF_NT = 1024;
+constexpr u32 GF_WIN = SORT_TILE + 2 * GF_HALO;
+constexpr u32 GF_PER = (GF_WIN + GF_NT - 1) / GF_NT;
+
+template <bool HASV>
+__global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restrict__ src,
+                                                    const u32* __restrict__ srcv, u64* __restrict__ dst,
+                                                    u32* __restrict__ dstv) {
+  constexpr uint16_t NONE = 0xFFFF;
+  __shared__ u64 s_k[GF_WIN];
+  __shared__ uint16_t s_gs[GF_WIN];  // window position of the group's start, or NONE
+  __shared__ uint16_t s_ge[GF_WIN];  // window position of the next group's start, or NONE
+  __shared__ int s_w[GF_NT / 64];
+  __shared__ u32 s_blk;
+  const u32 tid = threadIdx.x;
+  const u32 t = blockIdx.x;
+  if (t >= p.tstart[p.NB]) return;
+  if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t);
+  __syncthreads();
+  const u32 blk = s_blk;
+  const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
+  const u64 ts = bs + (u64)(t - p.tstart[blk]) * SORT_TILE;
+  const u64 te = be - ts < (u64)SORT_TILE ? be : ts + SORT_TILE;
+  const u64 ws = ts - bs > GF_HALO ? ts - GF_HALO : bs;
+  const u64 we = be - te > GF_HALO ? te + GF_HALO : be;
+  const u32 wn = (u32)(we - ws);
+  const bool wfirst = ws == bs, wlast = we == be;
+  for (u32 i = tid; i < wn; i += GF_NT) s_k[i] = src[ws + i];
+  __syncthreads();
+  // Position w starts a group when it is the block's first key or its top
+  // bits differ from those at w - 1; the window's first position inside a
+  // block is no start (a group reaching past it counts as large).
+  auto head = [&](u32 w) -> bool { return w == 0 ? wfirst : (s_k[w] >> GF_SHIFT) != (s_k[w - 1] >> GF_SHIFT); };
+  const u32 c0 = tid * GF_PER;
+  int last = -1, first = 0x7FFFFFFF;
+  for (u32 k = 0; k < GF_PER; ++k) {
+    const u32 w = c0 + k;
+    if (w < wn && head(w)) {
+      last = (int)w;
+      if (first == 0x7FFFFFFF) first = (int)w;
+    }
+  }
+  const int before = block_exclusive_extreme<GF_NT, true>(last, s_w);
+  const int after = block_exclusive_extreme<GF_NT, false>(first, s_w);
+  {
+    int cur = before;
+    for (u32 k = 0; k < GF_PER; ++k) {
+      const u32 w = c0 + k;
+      if (w >= wn) break;
+      if (head(w)) cur = (int)w;
+      s_gs[w] = cur < 0 ? NONE : (uint16_t)cur;
+    }
+    // the block's end counts as a group start
+    cur = after != 0x7FFFFFFF ? after : (wlast ? (int)wn : -1);
+    for (int k = (int)GF_PER - 1; k >= 0; --k) {
+      const u32 w = c0 + (u32)k;
+      if (w >= wn) continue;
+      s_ge[w] = cur < 0 ? NONE : (uint16_t)cur;
+      if (head(w)) cur = (int)w;
+    }
+  }
+  __syncthreads();
+  bool bad = false;
+  const u32 o1 = (u32)(te - ws);
+  for (u32 w = (u32)(ts - ws) + tid; w < o1; w += GF_NT) {
+    const u64 key = s_k[w];
+    const u32 gs = s_gs[w], ge = s_ge[w];
+    u32 o = w;
+    if (gs != NONE && ge != NONE && ge - gs <= GF_HALO) {
+      u32 r = 0;
+      for (u32 j = gs; j < ge; ++j) {
+        const u64 kj = s_k[j];
+        r += (kj < key || (kj == key && j < w)) ? 1u : 0u;
+      }
+      o = gs + r;
+    } else if (gs != w && s_k[w - 1] != key) {
+      bad = true;  // a large group with different keys (w >= 1: w = 0 only at a block start)
+    }
+    dst[ws + o] = key;
+    if (HASV) dstv[ws + o] = srcv[ws + w];
+  }
+  if (bad) p.gflags[blk] = 1u;
+}
+
+template <bool HASV>
+void launch_group_fix(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s) {
+  if (p.max_tiles == 0) return;
+  const int pe_ = prof_begin(s);
+  hipLaunchKernelGGL(k_group_fix<HASV>, dim3(p.max_tiles), dim3(GF_NT), 0, s, p, src, srcv, dst, dstv);
+  prof_end(pe_, "group_fix", s);
+}
+template void launch_group_fix<false>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
+template void launch_group_fix<true>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
 
 // ----------------------------------------------------------------- small blocks
 // A block of at most one tile is sorted entirely in LDS: all digit passes,

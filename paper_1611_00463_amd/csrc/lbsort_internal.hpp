@@ -79,6 +79,9 @@ struct Plan {
   u32* large_list;       // [NB] blocks larger than one tile, in block order
   u32* rem_prefix;       // [NB+1] over large blocks: prefix of (tiles - C_RMIN)
   TileDesc* tdesc;       // [max_tiles] by status slot (queue base + ticket)
+  const u32* only;       // [NB] or null: plan only the large blocks with only[b] != 0
+  u32 epoch_base;        // added to the look-back epochs of the radix passes
+  u32* gflags;           // [NB] blocks the group fix-up could not finish
   u32* counters;         // [C_COUNT]
   u32* hist;             // [NB][D][256]
   u64* status;           // [max_tiles][256]

@@ -135,3 +135,40 @@ def test_repeat_runs_identical(ws):
         else:
             for a, b in zip(first, cur):
                 np.testing.assert_array_equal(a, b)
+
+
+# ---------------------------------------------------------------- local sort paths
+# 64-bit keys are sorted locally by their three highest digits and a fix-up of
+# the groups of equal top 24 bits; blocks with a large group of different keys
+# are sorted again over all eight digits.  These inputs reach every branch.
+def _top_small_keys(n, seed, top_values):
+    low = datagen.uniform_keys(n, seed=seed) >> np.uint64(24)          # 40 random low bits
+    pick = datagen.uniform_keys(n, seed=seed + 1) % np.uint64(len(top_values))
+    return (np.asarray(top_values, dtype=np.uint64)[pick] << np.uint64(40)) | low
+
+
+@pytest.mark.parametrize("case", ["all_below_2_40", "half_blocks", "medium_groups", "small_groups"])
+def test_local_sort_group_paths(ws, case):
+    n, P = 1_000_000, 8
+    if case == "all_below_2_40":          # one group per block with distinct keys: every block falls back
+        keys = datagen.uniform_keys(n, seed=41) >> np.uint64(24)
+    elif case == "half_blocks":           # blocks 0-3 fall back, blocks 4-7 take the fix-up
+        keys = datagen.uniform_keys(n, seed=42)
+        keys[: n // 2] >>= np.uint64(24)
+    elif case == "medium_groups":         # 1000 top values: groups of ~125 keys per block
+        keys = _top_small_keys(n, 43, list(range(7, 7007, 7)))
+    else:                                  # 2^16 top values: groups of a few keys, many straddling tiles
+        keys = _top_small_keys(n, 44, list(range(0, 1 << 16)))
+    vals = datagen.index_values(n)
+    check_case(keys, vals, P, 0, ws=ws)
+
+
+def test_local_sort_paths_agree(ws, monkeypatch):
+    """The same bytes with the fix-up and with all eight radix passes."""
+    keys = datagen.uniform_keys(1 << 21, seed=45)
+    vals = datagen.index_values(1 << 21)
+    a = check_case(keys, vals, 16, 0, ws=ws)[0]
+    ka, va = to_host(a.keys).copy(), to_host(a.vals).copy()
+    monkeypatch.setenv("LBSORT_LOCAL_SORT", "lsd")
+    b = check_case(keys, vals, 16, 0, ws=ws)[0]
+    assert np.array_equal(ka, to_host(b.keys)) and np.array_equal(va, to_host(b.vals))
