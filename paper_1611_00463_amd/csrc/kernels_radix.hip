@@ -590,22 +590,20 @@ constexpr u32 GF_HALO = 64;
 constexpr u32 GF_SHIFT = 40;
 constexpr int GF_NT = 1024;
 constexpr u32 GF_WIN = SORT_TILE + 2 * GF_HALO;
-constexpr u32 GF_PER = (GF_WIN + GF_NT - 1) / GF_NT;
 
 template <bool HASV>
 __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restrict__ src,
                                                     const u32* __restrict__ srcv, u64* __restrict__ dst,
                                                     u32* __restrict__ dstv) {
-  constexpr uint16_t NONE = 0xFFFF;
+  constexpr u32 NW = GF_WIN / 64 + 2;  // head-bit words, with room for the block's end
   __shared__ u64 s_k[GF_WIN];
-  __shared__ uint16_t s_gs[GF_WIN];  // window position of the group's start, or NONE
-  __shared__ uint16_t s_ge[GF_WIN];  // window position of the next group's start, or NONE
-  __shared__ int s_w[GF_NT / 64];
+  __shared__ u64 s_hb[NW];  // bit w: window position w starts a group
   __shared__ u32 s_blk;
-  const u32 tid = threadIdx.x;
+  const u32 tid = threadIdx.x, lane = tid & 63;
   const u32 t = blockIdx.x;
   if (t >= p.tstart[p.NB]) return;
   if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t);
+  for (u32 i = tid; i < NW; i += GF_NT) s_hb[i] = 0;
   __syncthreads();
   const u32 blk = s_blk;
   const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
@@ -619,44 +617,34 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restri
   __syncthreads();
   // Position w starts a group when it is the block's first key or its top
   // bits differ from those at w - 1; the window's first position inside a
-  // block is no start (a group reaching past it counts as large).
-  auto head = [&](u32 w) -> bool { return w == 0 ? wfirst : (s_k[w] >> GF_SHIFT) != (s_k[w - 1] >> GF_SHIFT); };
-  const u32 c0 = tid * GF_PER;
-  int last = -1, first = 0x7FFFFFFF;
-  for (u32 k = 0; k < GF_PER; ++k) {
-    const u32 w = c0 + k;
-    if (w < wn && head(w)) {
-      last = (int)w;
-      if (first == 0x7FFFFFFF) first = (int)w;
-    }
-  }
-  const int before = block_exclusive_extreme<GF_NT, true>(last, s_w);
-  const int after = block_exclusive_extreme<GF_NT, false>(first, s_w);
-  {
-    int cur = before;
-    for (u32 k = 0; k < GF_PER; ++k) {
-      const u32 w = c0 + k;
-      if (w >= wn) break;
-      if (head(w)) cur = (int)w;
-      s_gs[w] = cur < 0 ? NONE : (uint16_t)cur;
-    }
-    // the block's end counts as a group start
-    cur = after != 0x7FFFFFFF ? after : (wlast ? (int)wn : -1);
-    for (int k = (int)GF_PER - 1; k >= 0; --k) {
-      const u32 w = c0 + (u32)k;
-      if (w >= wn) continue;
-      s_ge[w] = cur < 0 ? NONE : (uint16_t)cur;
-      if (head(w)) cur = (int)w;
-    }
+  // block is no start (a group reaching past it counts as large), and the
+  // block's end counts as one.  One ballot per 64 positions.
+  for (u32 base = 0; base < wn + 1; base += GF_NT) {
+    const u32 w = base + tid;
+    bool h = false;
+    if (w < wn) h = w == 0 ? wfirst : (s_k[w] >> GF_SHIFT) != (s_k[w - 1] >> GF_SHIFT);
+    else if (w == wn) h = wlast;
+    const u64 m = __ballot(h);
+    if (lane == 0 && w < wn + 64) s_hb[w >> 6] = m;
   }
   __syncthreads();
   bool bad = false;
   const u32 o1 = (u32)(te - ws);
   for (u32 w = (u32)(ts - ws) + tid; w < o1; w += GF_NT) {
     const u64 key = s_k[w];
-    const u32 gs = s_gs[w], ge = s_ge[w];
+    // group bounds within 64 positions: the last start at or before w and the
+    // first start after it (a group of at most GF_HALO keys has both there)
+    const u32 wi = w >> 6, b = w & 63;
+    const u64 upto = ((u64)2 << b) - 1;  // bits 0..b
+    u32 gs = 0xFFFFFFFFu, ge = 0xFFFFFFFFu;
+    u64 m = s_hb[wi] & upto;
+    if (m) gs = wi * 64 + 63 - (u32)__clzll((long long)m);
+    else if (wi > 0 && (m = s_hb[wi - 1]) != 0) gs = (wi - 1) * 64 + 63 - (u32)__clzll((long long)m);
+    m = s_hb[wi] & ~upto;
+    if (m) ge = wi * 64 + (u32)__ffsll((long long)m) - 1;
+    else if ((m = s_hb[wi + 1]) != 0) ge = (wi + 1) * 64 + (u32)__ffsll((long long)m) - 1;
     u32 o = w;
-    if (gs != NONE && ge != NONE && ge - gs <= GF_HALO) {
+    if (gs != 0xFFFFFFFFu && ge != 0xFFFFFFFFu && ge - gs <= GF_HALO) {
       u32 r = 0;
       for (u32 j = gs; j < ge; ++j) {
         const u64 kj = s_k[j];
