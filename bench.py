@@ -57,6 +57,8 @@ def kernel_bytes_per_launch(name, n, kb, vb):
         return n * 2 * (kb + vb)          # read key+value, write key+value
     if name == "hist":
         return n * kb                     # read keys once for all digit counts
+    if name == "group_fix":
+        return n * 2 * (kb + vb)          # read keys and values, write them once
     return None
 
 

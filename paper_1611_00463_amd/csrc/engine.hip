@@ -18,7 +18,7 @@ namespace lbs {
 void launch_plan(const Plan& p, hipStream_t s);
 void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s);
 template <typename K>
-void launch_hist(const Plan& p, const K* src, hipStream_t s);
+void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo = 0);
 template <typename K, bool HASV>
 void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s);
 template <typename K, bool HASV>
@@ -279,11 +279,13 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
     launch_fill32((u32*)p.status, sh.max_tiles * RADIX * 2, 0, st);
   }
   launch_plan(p, st);
-  if (sh.has_large) launch_hist<K>(p, kin, st);
+  // the fix-up path of 64-bit keys needs the counts of the three top digits only
+  const bool hybrid = sizeof(K) == 8 && hybrid_local_sort();
+  if (sh.has_large) launch_hist<K>(p, kin, st, hybrid ? 5u : 0u);
   if (sh.has_small) launch_small_sort<K, HASV>(p, kin, vin, dk(sh.D - 1), dv(sh.D - 1), st);
   if (sh.has_large) {
     if constexpr (sizeof(K) == 8) {
-      if (hybrid_local_sort()) {
+      if (hybrid) {
         // 64-bit keys: the three highest digits first (blocks grouped by their
         // top 24 bits), then the group fix-up into the step-1 output F; the
         // blocks it flags are sorted again over all eight digits.

@@ -227,7 +227,8 @@ __global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
 constexpr u32 HIST_TILES = 16;
 constexpr int LOOKBACK = 4;  // predecessors read per look-back round
 
-template <typename K>
+// Digit positions DLO..D-1 are counted (the others stay zero).
+template <typename K, int DLO>
 __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ src, u32 tpw) {
   constexpr int D = KeyT<K>::BITS / RADIX_BITS;
   __shared__ u32 h[D * RADIX];
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
           if (lane == (u32)(__ffsll((unsigned long long)hm) - 1)) {
             const u32 c = (u32)__popcll(hm);
 #pragma unroll
-            for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((hot >> (q * RADIX_BITS)) & (RADIX - 1))], c);
+            for (int q = DLO; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((hot >> (q * RADIX_BITS)) & (RADIX - 1))], c);
           }
           done = done || key == hot;
         }
@@ -291,13 +292,13 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
         if (lane == (u32)leader) {
           const u32 c = (u32)__popcll(sm);
 #pragma unroll
-          for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((lk >> (q * RADIX_BITS)) & (RADIX - 1))], c);
+          for (int q = DLO; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((lk >> (q * RADIX_BITS)) & (RADIX - 1))], c);
         }
         done = done || same;
       }
       if (!done) {
 #pragma unroll
-        for (int q = 0; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1))], 1u);
+        for (int q = DLO; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1))], 1u);
       }
     }
   }
@@ -613,7 +614,31 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restri
   const u64 we = be - te > GF_HALO ? te + GF_HALO : be;
   const u32 wn = (u32)(we - ws);
   const bool wfirst = ws == bs, wlast = we == be;
-  for (u32 i = tid; i < wn; i += GF_NT) s_k[i] = src[ws + i];
+  // all loads issued at once: the window's keys (into LDS) and this thread's
+  // values of the tile (kept in registers until the write)
+  constexpr int KL = (GF_WIN + GF_NT - 1) / GF_NT, VL = SORT_TILE / GF_NT;
+  const u32 o0 = (u32)(ts - ws), o1 = (u32)(te - ws);
+  u32 v[HASV ? VL : 1];
+  if (HASV) {
+#pragma unroll
+    for (int k = 0; k < VL; ++k) {
+      const u32 w = o0 + (u32)k * GF_NT + tid;
+      v[k] = w < o1 ? srcv[ws + w] : 0u;
+    }
+  }
+  {
+    u64 kk[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const u32 i = (u32)k * GF_NT + tid;
+      kk[k] = i < wn ? src[ws + i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const u32 i = (u32)k * GF_NT + tid;
+      if (i < wn) s_k[i] = kk[k];
+    }
+  }
   __syncthreads();
   // Position w starts a group when it is the block's first key or its top
   // bits differ from those at w - 1; the window's first position inside a
@@ -629,8 +654,10 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restri
   }
   __syncthreads();
   bool bad = false;
-  const u32 o1 = (u32)(te - ws);
-  for (u32 w = (u32)(ts - ws) + tid; w < o1; w += GF_NT) {
+#pragma unroll
+  for (int k = 0; k < VL; ++k) {
+    const u32 w = o0 + (u32)k * GF_NT + tid;
+    if (w >= o1) break;
     const u64 key = s_k[w];
     // group bounds within 64 positions: the last start at or before w and the
     // first start after it (a group of at most GF_HALO keys has both there)
@@ -655,7 +682,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restri
       bad = true;  // a large group with different keys (w >= 1: w = 0 only at a block start)
     }
     dst[ws + o] = key;
-    if (HASV) dstv[ws + o] = srcv[ws + w];
+    if (HASV) dstv[ws + o] = v[k];
   }
   if (bad) p.gflags[blk] = 1u;
 }
@@ -742,11 +769,11 @@ __global__ __launch_bounds__(SORT_NT) void k_small_sort(Plan p, const K* __restr
 
 // ----------------------------------------------------------------- launchers
 void launch_plan(const Plan& p, hipStream_t s) {
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, p); prof_end(pe_, "plan", s); }
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, p); prof_end(pe_, p.only ? "plan_fallback" : "plan", s); }
   if (p.max_tiles) {
     const int pe_ = prof_begin(s);
     hipLaunchKernelGGL(k_tile_desc, dim3((p.max_tiles + 255) / 256), dim3(256), 0, s, p);
-    prof_end(pe_, "tile_desc", s);
+    prof_end(pe_, p.only ? "tile_desc_fallback" : "tile_desc", s);
   }
 }
 
@@ -758,14 +785,17 @@ void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s) {
 }
 
 template <typename K>
-void launch_hist(const Plan& p, const K* src, hipStream_t s) {
+void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo) {
   if (p.max_tiles == 0) return;
   // tiles per workgroup: up to HIST_TILES, but at least a few workgroups per compute unit
   u32 tpw = p.max_tiles / p.persist_wgs;
   tpw = tpw < 1 ? 1 : (tpw > HIST_TILES ? HIST_TILES : tpw);
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_hist<K>, dim3((p.max_tiles + tpw - 1) / tpw), dim3(SORT_NT), 0, s, p, src, tpw); prof_end(pe_, "hist", s); }
+  { const int pe_ = prof_begin(s); if (sizeof(K) == 8 && dlo == 5)
+      hipLaunchKernelGGL((k_hist<K, 5>), dim3((p.max_tiles + tpw - 1) / tpw), dim3(SORT_NT), 0, s, p, src, tpw);
+    else
+      hipLaunchKernelGGL((k_hist<K, 0>), dim3((p.max_tiles + tpw - 1) / tpw), dim3(SORT_NT), 0, s, p, src, tpw); prof_end(pe_, p.only ? "hist_fallback" : "hist", s); }
   const u32 waves = p.NB * p.D;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_scan_hist, dim3((waves + 3) / 4), dim3(256), 0, s, p); prof_end(pe_, "scan_hist", s); }
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_scan_hist, dim3((waves + 3) / 4), dim3(256), 0, s, p); prof_end(pe_, p.only ? "scan_hist_fallback" : "scan_hist", s); }
 }
 
 template <typename K, bool HASV>
@@ -783,11 +813,11 @@ void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* 
   grid = grid < p.max_tiles ? grid : p.max_tiles;
   grid = (grid + p.nq - 1) / p.nq * p.nq;
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, 1>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst, dstv,
-                     pass); prof_end(pe_, "onesweep", s); }
+                     pass); prof_end(pe_, p.only ? "onesweep_fallback" : "onesweep", s); }
 }
 
 #define LBS_INST(K)                                                                                     \
-  template void launch_hist<K>(const Plan&, const K*, hipStream_t);                                   \
+  template void launch_hist<K>(const Plan&, const K*, hipStream_t, u32);                                   \
   template void launch_small_sort<K, false>(const Plan&, const K*, const u32*, K*, u32*, hipStream_t); \
   template void launch_small_sort<K, true>(const Plan&, const K*, const u32*, K*, u32*, hipStream_t);  \
   template void launch_onesweep<K, false>(const Plan&, const K*, const u32*, K*, u32*, u32, hipStream_t); \
