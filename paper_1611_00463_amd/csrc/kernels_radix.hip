@@ -371,7 +371,10 @@ __device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n,
 // hands workgroups to the XCDs round-robin), then helps the other queues.
 // A tile waits only for tiles of its own queue with smaller tickets, which
 // running workgroups hold, so the waits always end.
-template <typename K, bool HASV, int NT, int ITEMS, int MINW>
+// REDO: a pass of the fallback plan (blocks the group fix-up flagged); it is
+// a separate instantiation so that profiles tell the two apart, and it leaves
+// at once when the plan holds no block.
+template <typename K, bool HASV, int NT, int ITEMS, int MINW, bool REDO>
 __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restrict__ src,
                                                  const u32* __restrict__ srcv, K* __restrict__ dst,
                                                  u32* __restrict__ dstv, u32 pass) {
@@ -411,6 +414,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
   const u32 shift = pass * RADIX_BITS;
   const u32 epoch = pass + 1 + p.epoch_base;
   const u32 nq = p.nq;
+  if (REDO && p.counters[C_NLARGE] == 0) return;
   for (u32 qi = 0; qi < nq; ++qi) {
     const u32 x = (blockIdx.x + qi) % nq;
     const TileQueue Q{x, nq, p.counters[C_QPARAM + 4 * x], p.counters[C_QPARAM + 4 * x + 1], p.rem_prefix};
@@ -812,8 +816,14 @@ void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* 
   u32 grid = p.persist_wgs * 256 / NT;
   grid = grid < p.max_tiles ? grid : p.max_tiles;
   grid = (grid + p.nq - 1) / p.nq * p.nq;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, 1>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst, dstv,
-                     pass); prof_end(pe_, p.only ? "onesweep_fallback" : "onesweep", s); }
+  const int pe_ = prof_begin(s);
+  if (p.only)
+    hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, 1, true>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst,
+                       dstv, pass);
+  else
+    hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, 1, false>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst,
+                       dstv, pass);
+  prof_end(pe_, p.only ? "onesweep_fallback" : "onesweep", s);
 }
 
 #define LBS_INST(K)                                                                                     \
