@@ -8,8 +8,9 @@ It is a plain, slow, step-by-step rendering of the six steps of Section IV
 ("Programming Model"), on one machine, with the P processors of the paper as P
 virtual processors over contiguous blocks of one array.  numpy's stable sort
 and ``searchsorted`` are used as library primitives; everything else is
-written out in the paper's order.  Keys are unsigned integers (uint32 or
-uint64) compared as unsigned; values are opaque uint32 payloads.
+written out in the paper's order.  Keys are 32- or 64-bit integers,
+unsigned or signed, compared by numpy in their own order (floating-point keys
+go through ``oracle.typed``); values are opaque uint32 payloads.
 
 Readings where the paper is silent (each is listed with its reason in the
 design notes of the repository):
@@ -272,7 +273,7 @@ def sample_sort(keys: np.ndarray, vals: np.ndarray | None, P: int, s: int = 0,
     """The whole method on one array: steps 1 to 6 of Section IV."""
     keys = np.asarray(keys)
     dtype = keys.dtype
-    assert dtype in (np.uint32, np.uint64)
+    assert dtype in (np.uint32, np.uint64, np.int32, np.int64)
     N = len(keys)
     if s <= 0:
         s = default_sample_count(P, dtype.itemsize)
