@@ -19,9 +19,15 @@
  *      Fig. 2), yielding the globally sorted data; smaller keys sit in
  *      partitions with smaller ids (Section IV.C).
  *
- * Keys are unsigned 32- or 64-bit integers in ascending unsigned order.
- * Values are opaque 32-bit payloads carried with their keys.  In the default
- * investigator mode (COUNT) the output equals a stable sort of the input.
+ * Keys are 32- or 64-bit unsigned integers, signed integers or IEEE floats
+ * (the interface is generic over the data type, Section IV.C), sorted
+ * ascending in their type's order; floats in IEEE 754-2008 totalOrder:
+ * -NaN < -inf < negative numbers < -0 < +0 < positive numbers < +inf < +NaN.
+ * Values are opaque 32-bit payloads carried with their keys, or generated:
+ * with LBSORT_VAL_INDEX each key carries its input position (inside its
+ * instance), which gives the provenance of every sorted entry (step 6 and
+ * Section IV.C).  In the default investigator mode (COUNT) the output equals
+ * a stable sort of the input.
  *
  * Conventions shared by every entry point
  *   - All data pointers are DEVICE pointers unless marked "host".
@@ -60,11 +66,20 @@ extern "C" {
 #define LBSORT_ERR_OOM (-5)
 #define LBSORT_ERR_DEVICE (-6)
 
-/* key and value types */
-#define LBSORT_U32 1
-#define LBSORT_U64 2
-#define LBSORT_NOVAL 0
-#define LBSORT_VAL_U32 1
+/* key types */
+#define LBSORT_U32 1 /* uint32_t                                       */
+#define LBSORT_U64 2 /* uint64_t                                       */
+#define LBSORT_I32 3 /* int32_t, two's complement                      */
+#define LBSORT_I64 4 /* int64_t                                        */
+#define LBSORT_F32 5 /* IEEE binary32, totalOrder                      */
+#define LBSORT_F64 6 /* IEEE binary64, totalOrder                      */
+/* value types */
+#define LBSORT_NOVAL 0     /* keys only                                               */
+#define LBSORT_VAL_U32 1   /* one uint32_t payload per key from vals_in                */
+#define LBSORT_VAL_INDEX 2 /* vals_in ignored; vals_out receives each key's input
+                              position inside its instance (uint32_t; instances of
+                              at most 2^32 keys, else LBSORT_ERR_UNSUPPORTED for one
+                              instance, the device error E_RANGE for a batch)       */
 
 /* investigator modes (step 4, Section IV.B) */
 #define LBSORT_INV_COUNT 0 /* default: equal-key runs split at global ranks floor(kN/P) */
@@ -108,7 +123,8 @@ int lbsort_sort_keys(int key_type, const void *keys_in, void *keys_out, uint64_t
                      const lbsort_params *params, const lbsort_parts *parts, void *ws,
                      size_t *ws_bytes, void *stream);
 
-/* Same, carrying one 32-bit value per key (val_type = LBSORT_VAL_U32). */
+/* Same, carrying one 32-bit value per key: from vals_in (LBSORT_VAL_U32) or
+ * the key's input position (LBSORT_VAL_INDEX, vals_in ignored). */
 int lbsort_sort_pairs(int key_type, int val_type, const void *keys_in, const void *vals_in,
                       void *keys_out, void *vals_out, uint64_t n, const lbsort_params *params,
                       const lbsort_parts *parts, void *ws, size_t *ws_bytes, void *stream);
@@ -138,6 +154,39 @@ int lbsort_local_sort(int key_type, int val_type, const void *keys_in, const voi
                       void *keys_out, void *vals_out, const uint64_t *seg_offsets, uint32_t B,
                       uint64_t total_n, const lbsort_params *params, void *ws, size_t *ws_bytes,
                       void *stream);
+
+/*
+ * Binary search over sorted data (Section III, Section IV.C: the sorted
+ * result can be searched).  sorted_keys: n keys of key_type in ascending
+ * order of that type, e.g. the keys_out of a sort; queries: nq keys of the
+ * same type.  For every query j:
+ *   pos_out[j]  = number of sorted keys < queries[j] (upper = 0) or
+ *                 <= queries[j] (upper = 1), compared in the key type's order
+ *                 (floats: totalOrder, so -0 < +0 and NaNs are ordered too);
+ *   part_out[j] = the partition k with part_offsets[k] <= pos_out[j] <
+ *                 part_offsets[k+1] (the processor that holds that position),
+ *                 or P when pos_out[j] = n.  part_out may be NULL; if not,
+ *                 part_offsets ([P+1] device, as written by a sort) is required.
+ * All arrays are device memory owned by the caller; nothing is allocated.
+ * Unsorted input gives unspecified positions but never reads out of range.
+ */
+int lbsort_search(int key_type, const void *sorted_keys, uint64_t n, const void *queries, uint64_t nq,
+                  int upper, const uint64_t *part_offsets, uint32_t P, uint64_t *pos_out,
+                  uint32_t *part_out, void *stream);
+
+/*
+ * Provenance of sorted entries (step 6 of Section IV keeps, for every entry,
+ * the processor and the index it came from; Section IV.C exposes them).
+ * src_index: count input positions (the vals_out of an LBSORT_VAL_INDEX sort
+ * of n keys over P processors).  For each g = src_index[j] < n:
+ *   src_block[j]  = the block (processor) i whose input range
+ *                   [floor(i n / P), floor((i+1) n / P)) holds g;
+ *   src_offset[j] = g - floor(i n / P), the index inside that block.
+ * Positions >= n give 0xFFFFFFFF in both.  Either output may be NULL (not
+ * both).  n <= 2^32.  Device arrays owned by the caller; nothing allocated.
+ */
+int lbsort_provenance(const uint32_t *src_index, uint64_t count, uint64_t n, uint32_t P,
+                      uint32_t *src_block, uint32_t *src_offset, void *stream);
 
 /*
  * Synchronise `stream` and return the device error latched in `ws` by the

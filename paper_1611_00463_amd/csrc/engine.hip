@@ -30,6 +30,12 @@ void launch_split(const Plan& p, const K* sorted, u64 max_samples, const void* o
                   void* out_send, void* out_cuts, void* out_split, hipStream_t s);
 template <typename K, bool HASV>
 void launch_merge_level(const Plan& p, u32 level, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s);
+template <typename K>
+void launch_key_out(K* a, u64 n, u64 top, u64 fm, hipStream_t s);
+template <typename K>
+void launch_search(const K* a, u64 n, const K* q, u64 nq, bool upper, u64 top, u64 fm, const u64* G, u32 P,
+                   u64* pos, u32* part, hipStream_t s);
+void launch_provenance(const u32* idx, u64 count, u64 n, u32 P, u32* blk, u32* off, hipStream_t s);
 
 static thread_local std::string g_last_error;
 
@@ -52,6 +58,28 @@ __global__ void k_seg2(u64* seg, u64 n) {
 }
 
 static inline u64 align256(u64 x) { return (x + 255) & ~(u64)255; }
+
+// Key types: width in bytes (0 for an unknown type) and the masks of the
+// order-preserving map onto unsigned integers (key_in in the kernels):
+// signed integers flip the sign bit, IEEE floats flip the sign bit of
+// non-negative numbers and every bit of negative ones (totalOrder).
+static u32 key_width(int t) {
+  switch (t) {
+    case LBSORT_U32: case LBSORT_I32: case LBSORT_F32: return 4;
+    case LBSORT_U64: case LBSORT_I64: case LBSORT_F64: return 8;
+    default: return 0;
+  }
+}
+static void key_masks(int t, u64& top, u64& fm) {
+  const u32 w = key_width(t);
+  const u64 sign = w == 8 ? (1ull << 63) : (1ull << 31);
+  top = fm = 0;
+  if (t == LBSORT_I32 || t == LBSORT_I64) top = sign;
+  if (t == LBSORT_F32 || t == LBSORT_F64) {
+    top = sign;
+    fm = sign - 1;
+  }
+}
 
 // Compute units of the current device (cached per device).
 // The local sort of 64-bit keys: top three digits plus the group fix-up
@@ -94,7 +122,7 @@ struct Layout {
 
 static Layout make_layout(const Shape& sh) {
   Layout l;
-  const u64 K = sh.key_type == LBSORT_U64 ? 8 : 4;
+  const u64 K = key_width(sh.key_type);
   const u64 NB = (u64)sh.B * sh.P, P = sh.P, B = sh.B;
   u64 o = 0;
   auto take = [&](u64 bytes) {
@@ -140,10 +168,13 @@ static Layout make_layout(const Shape& sh) {
 
 static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbsort_params* prm, bool local_only,
                       Shape& sh) {
-  if (key_type != LBSORT_U32 && key_type != LBSORT_U64)
-    return fail(LBSORT_ERR_INVALID_ARG, "key_type must be LBSORT_U32 or LBSORT_U64 (got %d)", key_type);
-  if (val_type != LBSORT_NOVAL && val_type != LBSORT_VAL_U32)
-    return fail(LBSORT_ERR_INVALID_ARG, "val_type must be LBSORT_NOVAL or LBSORT_VAL_U32 (got %d)", val_type);
+  if (!key_width(key_type))
+    return fail(LBSORT_ERR_INVALID_ARG, "key_type must be one of LBSORT_U32..LBSORT_F64 (got %d)", key_type);
+  if (val_type != LBSORT_NOVAL && val_type != LBSORT_VAL_U32 && val_type != LBSORT_VAL_INDEX)
+    return fail(LBSORT_ERR_INVALID_ARG, "val_type must be LBSORT_NOVAL, LBSORT_VAL_U32 or LBSORT_VAL_INDEX (got %d)",
+                val_type);
+  if (val_type == LBSORT_VAL_INDEX && B == 1 && total_n > (1ull << 32))
+    return fail(LBSORT_ERR_UNSUPPORTED, "LBSORT_VAL_INDEX needs n <= 2^32 (32-bit positions)");
   lbsort_params d = {1, 0, LBSORT_INV_COUNT, 0, 0, 0};
   const lbsort_params& p = prm ? *prm : d;
   if (p.P < 1 || p.P > LBSORT_MAX_P) return fail(LBSORT_ERR_INVALID_ARG, "P must be in [1, %d] (got %u)", LBSORT_MAX_P, p.P);
@@ -164,14 +195,16 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   sh.total_n = total_n;
   sh.inv = p.investigator;
   sh.local_only = local_only;
-  const u32 kb = key_type == LBSORT_U64 ? 8 : 4;
+  const u32 kb = key_width(key_type);
   sh.D = kb * 8 / RADIX_BITS;
   // default budget: the largest multiple of P samples within one 256 KB read
   // buffer over all processors (that budget itself when it is below P)
   const u32 budget = 262144u / (p.P * kb);
   sh.s = p.s ? p.s : (budget >= p.P ? budget / p.P * p.P : (budget > 0 ? budget : 1u));
   // merge fan-in and tile: explicit, else tuned, else defaults
-  Tuned tu = tuning_lookup(key_type, val_type, total_n / B, B, p.P);
+  // tuned settings depend on the widths only
+  Tuned tu = tuning_lookup(kb == 8 ? LBSORT_U64 : LBSORT_U32, val_type ? LBSORT_VAL_U32 : LBSORT_NOVAL, total_n / B, B,
+                           p.P);
   u32 F = p.fanin ? p.fanin : tu.fanin;
   if (!F) {
     F = 2;
@@ -260,6 +293,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.grp_out = (u64*)(ws + lay.grp_out);
   p.ng_max = sh.ng0;
   p.mtiles_max = (u32)sh.mtiles;
+  p.vidx = sh.val_type == LBSORT_VAL_INDEX;
   if (seg_in) {
     p.seg = seg_in;
   } else {
@@ -267,6 +301,15 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
     hipLaunchKernelGGL(k_seg2, dim3(1), dim3(64), 0, st, seg, sh.total_n);
     p.seg = seg;
   }
+  // launches that read keys_in map the keys (px); those that write keys_out
+  // or the splitters map them back (py)
+  u64 top, fm;
+  key_masks(sh.key_type, top, fm);
+  Plan px = p, py = p;
+  px.kx_top = top;
+  px.kx_fm = fm;
+  py.ky_top = top;
+  py.ky_fm = fm;
   K* tk = (K*)(ws + lay.tmpk);
   u32* tv = (u32*)(ws + lay.tmpv);
   const u32 S = sh.D + sh.L;
@@ -281,8 +324,8 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   launch_plan(p, st);
   // the fix-up path of 64-bit keys needs the counts of the three top digits only
   const bool hybrid = sizeof(K) == 8 && hybrid_local_sort();
-  if (sh.has_large) launch_hist<K>(p, kin, st, hybrid ? 5u : 0u);
-  if (sh.has_small) launch_small_sort<K, HASV>(p, kin, vin, dk(sh.D - 1), dv(sh.D - 1), st);
+  if (sh.has_large) launch_hist<K>(px, kin, st, hybrid ? 5u : 0u);
+  if (sh.has_small) launch_small_sort<K, HASV>(px, kin, vin, dk(sh.D - 1), dv(sh.D - 1), st);
   if (sh.has_large) {
     if constexpr (sizeof(K) == 8) {
       if (hybrid) {
@@ -294,7 +337,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         K* const O = F == kout ? tk : kout;
         u32* const OV = HASV ? (FV == vout ? tv : vout) : nullptr;
         launch_fill32(p.gflags, p.NB, 0, st);
-        launch_onesweep<K, HASV>(p, kin, vin, O, OV, 5, st);
+        launch_onesweep<K, HASV>(px, kin, vin, O, OV, 5, st);
         launch_onesweep<K, HASV>(p, O, OV, F, FV, 6, st);
         launch_onesweep<K, HASV>(p, F, FV, O, OV, 7, st);
         launch_group_fix<HASV>(p, (const u64*)O, OV, (u64*)F, FV, st);
@@ -303,27 +346,33 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         q.epoch_base = 8;  // the status words of the passes above stay valid for epochs 6..8
         launch_fill32(p.counters + C_TICKET, NQ * sh.D, 0, st);
         launch_plan(q, st);
+        Plan qx = q;
+        qx.kx_top = top;
+        qx.kx_fm = fm;
         launch_fill32(p.hist, (u64)p.NB * sh.D * RADIX, 0, st);
-        launch_hist<K>(q, kin, st);
+        launch_hist<K>(qx, kin, st);
         for (u32 j = 0; j < sh.D; ++j)
-          launch_onesweep<K, HASV>(q, j ? (j % 2 ? O : F) : kin, j ? (j % 2 ? OV : FV) : vin, j % 2 ? F : O,
+          launch_onesweep<K, HASV>(j ? q : qx, j ? (j % 2 ? O : F) : kin, j ? (j % 2 ? OV : FV) : vin, j % 2 ? F : O,
                                    j % 2 ? FV : OV, j, st);
       } else {
         for (u32 j = 0; j < sh.D; ++j)
-          launch_onesweep<K, HASV>(p, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);
+          launch_onesweep<K, HASV>(j ? p : px, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);
       }
     } else {
       for (u32 j = 0; j < sh.D; ++j)
-        launch_onesweep<K, HASV>(p, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);
+        launch_onesweep<K, HASV>(j ? p : px, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);
     }
   }
   if (!sh.local_only) {
     const K* sorted = dk(sh.D - 1);
-    launch_split<K>(p, sorted, sh.max_samples, parts->part_offsets, parts->part_counts, parts->send_counts,
+    launch_split<K>(py, sorted, sh.max_samples, parts->part_offsets, parts->part_counts, parts->send_counts,
                     parts->cuts, parts->splitters, st);
     for (u32 l = 0; l < sh.L; ++l)
-      launch_merge_level<K, HASV>(p, l, dk(sh.D - 1 + l), dv(sh.D - 1 + l), dk(sh.D + l), dv(sh.D + l), st);
+      launch_merge_level<K, HASV>(l + 1 == sh.L ? py : p, l, dk(sh.D - 1 + l), dv(sh.D - 1 + l), dk(sh.D + l),
+                                  dv(sh.D + l), st);
   }
+  // without a merge pass the local sort wrote keys_out: map it back in place
+  if (sh.L == 0 && (top | fm) != 0) launch_key_out<K>(kout, sh.total_n, top, fm, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
   return LBSORT_OK;
@@ -342,14 +391,18 @@ static int dispatch(const Shape& sh, const void* kin, const void* vin, void* kou
                 (unsigned long long)lay.total);
   if (((uintptr_t)ws & 255) != 0) return fail(LBSORT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (sh.total_n > 0 && (!kin || !kout)) return fail(LBSORT_ERR_INVALID_ARG, "keys_in/keys_out must not be NULL");
-  if (sh.val_type && sh.total_n > 0 && (!vin || !vout))
+  if (sh.val_type == LBSORT_VAL_U32 && sh.total_n > 0 && (!vin || !vout))
     return fail(LBSORT_ERR_INVALID_ARG, "vals_in/vals_out must not be NULL with LBSORT_VAL_U32");
+  if (sh.val_type == LBSORT_VAL_INDEX) {
+    if (sh.total_n > 0 && !vout) return fail(LBSORT_ERR_INVALID_ARG, "vals_out must not be NULL with LBSORT_VAL_INDEX");
+    vin = nullptr;  // the values are generated
+  }
   if (!sh.local_only && (!parts || !parts->part_offsets))
     return fail(LBSORT_ERR_INVALID_ARG, "parts->part_offsets is required");
   hipStream_t st = (hipStream_t)stream;
   char* w = (char*)ws;
-  const bool v = sh.val_type == LBSORT_VAL_U32;
-  if (sh.key_type == LBSORT_U64) {
+  const bool v = sh.val_type != LBSORT_NOVAL;
+  if (key_width(sh.key_type) == 8) {
     if (v) return run<u64, true>(sh, lay, (const u64*)kin, (const u32*)vin, (u64*)kout, (u32*)vout, seg, parts, w, st);
     return run<u64, false>(sh, lay, (const u64*)kin, nullptr, (u64*)kout, nullptr, seg, parts, w, st);
   }
@@ -399,6 +452,45 @@ int lbsort_local_sort(int key_type, int val_type, const void* keys_in, const voi
   if (rc) return rc;
   if (!seg_offsets) return fail(LBSORT_ERR_INVALID_ARG, "seg_offsets must not be NULL");
   return dispatch(sh, keys_in, vals_in, keys_out, vals_out, seg_offsets, nullptr, ws, ws_bytes, stream);
+}
+
+int lbsort_search(int key_type, const void* sorted_keys, uint64_t n, const void* queries, uint64_t nq, int upper,
+                  const uint64_t* part_offsets, uint32_t P, uint64_t* pos_out, uint32_t* part_out, void* stream) {
+  const u32 w = key_width(key_type);
+  if (!w) return fail(LBSORT_ERR_INVALID_ARG, "key_type must be one of LBSORT_U32..LBSORT_F64 (got %d)", key_type);
+  if (upper != 0 && upper != 1) return fail(LBSORT_ERR_INVALID_ARG, "upper must be 0 or 1 (got %d)", upper);
+  if (nq == 0) return LBSORT_OK;
+  if (!queries || !pos_out) return fail(LBSORT_ERR_INVALID_ARG, "queries/pos_out must not be NULL");
+  if (n > 0 && !sorted_keys) return fail(LBSORT_ERR_INVALID_ARG, "sorted_keys must not be NULL");
+  if (part_out && (!part_offsets || P < 1 || P > LBSORT_MAX_P))
+    return fail(LBSORT_ERR_INVALID_ARG, "part_out needs part_offsets and P in [1, %d]", LBSORT_MAX_P);
+  if (nq / 256 >= (1ull << 31)) return fail(LBSORT_ERR_UNSUPPORTED, "too many queries in one call");
+  u64 top, fm;
+  key_masks(key_type, top, fm);
+  hipStream_t st = (hipStream_t)stream;
+  if (w == 8)
+    launch_search<u64>((const u64*)sorted_keys, n, (const u64*)queries, nq, upper != 0, top, fm, part_offsets, P,
+                       pos_out, part_out, st);
+  else
+    launch_search<u32>((const u32*)sorted_keys, n, (const u32*)queries, nq, upper != 0, top, fm, part_offsets, P,
+                       pos_out, part_out, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return LBSORT_OK;
+}
+
+int lbsort_provenance(const uint32_t* src_index, uint64_t count, uint64_t n, uint32_t P, uint32_t* src_block,
+                      uint32_t* src_offset, void* stream) {
+  if (P < 1 || P > LBSORT_MAX_P) return fail(LBSORT_ERR_INVALID_ARG, "P must be in [1, %d] (got %u)", LBSORT_MAX_P, P);
+  if (n > (1ull << 32)) return fail(LBSORT_ERR_UNSUPPORTED, "n must be <= 2^32 (32-bit positions)");
+  if (count == 0) return LBSORT_OK;
+  if (!src_index || (!src_block && !src_offset))
+    return fail(LBSORT_ERR_INVALID_ARG, "src_index and one of src_block/src_offset must not be NULL");
+  if (count / 256 >= (1ull << 31)) return fail(LBSORT_ERR_UNSUPPORTED, "too many entries in one call");
+  launch_provenance(src_index, count, n, P, src_block, src_offset, (hipStream_t)stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return LBSORT_OK;
 }
 
 int lbsort_check(void* ws, void* stream) {

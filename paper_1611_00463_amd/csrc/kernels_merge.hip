@@ -300,9 +300,17 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
     __syncthreads();
   }
   const u64 out = p.rec_out[tile];
-  for (u32 q = tid; q < n; q += NT) {
-    dst[out + q] = s_k[pad8(q)];
-    if (HASV) dstv[out + q] = s_v[s_i[pad8(q)]];
+  if ((p.ky_top | p.ky_fm) == 0) {
+    for (u32 q = tid; q < n; q += NT) {
+      dst[out + q] = s_k[pad8(q)];
+      if (HASV) dstv[out + q] = s_v[s_i[pad8(q)]];
+    }
+  } else {
+    // the last pass of a signed or floating-point sort maps keys back
+    for (u32 q = tid; q < n; q += NT) {
+      dst[out + q] = key_out<K>(s_k[pad8(q)], p.ky_top, p.ky_fm);
+      if (HASV) dstv[out + q] = s_v[s_i[pad8(q)]];
+    }
   }
 }
 

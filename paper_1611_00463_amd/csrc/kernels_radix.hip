@@ -95,8 +95,11 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
     s_rmin = 0xFFFFFFFFu;
   }
   __syncthreads();
-  for (u32 b = tid; b < p.B; b += 1024)
+  for (u32 b = tid; b < p.B; b += 1024) {
     if (p.seg[b + 1] < p.seg[b]) s_bad = 1u;
+    // generated values are 32-bit input positions
+    else if (p.vidx && p.seg[b + 1] - p.seg[b] > (1ull << 32)) set_error(p.counters, E_RANGE);
+  }
   __syncthreads();
   const bool bad = s_bad != 0;
   if (bad && tid == 0) set_error(p.counters, E_SEG);
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
     for (int j = 0; j < SORT_TILE / SORT_NT; ++j) {
       const u32 idx = j * SORT_NT + tid;
       const bool valid = idx < tile_n;
-      const K key = valid ? src[tbase + idx] : (K)0;
+      const K key = valid ? key_in<K>(src[tbase + idx], p.kx_top, p.kx_fm) : (K)0;
       bool done = !valid;
       if (have_hot) {
         // the wave's hot key (a value seen in many lanes before) first
@@ -449,16 +452,23 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
 
       K keys[ITEMS];
       u32 vals[HASV ? ITEMS : 1];
+      // without a value array the values are the keys' input positions
+      // inside their instance
+      const u64 vgen = HASV && srcv == nullptr ? tbase - p.seg[blk / p.P] : 0;
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         const u32 idx = wbase + j * 64 + lane;
         if (idx < tile_n) {
           keys[j] = src[tbase + idx];
-          if (HASV) vals[j] = srcv[tbase + idx];
+          if (HASV) vals[j] = srcv ? srcv[tbase + idx] : (u32)(vgen + idx);
         } else {
           keys[j] = 0;
           if (HASV) vals[j] = 0;
         }
+      }
+      if ((p.kx_top | p.kx_fm) != 0) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) keys[j] = key_in<K>(keys[j], p.kx_top, p.kx_fm);
       }
       u32 rank[ITEMS];
       {
@@ -723,11 +733,12 @@ __global__ __launch_bounds__(SORT_NT) void k_small_sort(Plan p, const K* __restr
   const u32 wbase = w * WI;
   K keys[SORT_ITEMS];
   u32 vals[HASV ? SORT_ITEMS : 1];
+  const u64 vgen = HASV && srcv == nullptr ? bstart - p.seg[blk / p.P] : 0;
 #pragma unroll
   for (int j = 0; j < SORT_ITEMS; ++j) {
     const u32 idx = wbase + j * 64 + lane;
-    keys[j] = idx < n ? src[bstart + idx] : (K)0;
-    if (HASV) vals[j] = idx < n ? srcv[bstart + idx] : 0u;
+    keys[j] = idx < n ? key_in<K>(src[bstart + idx], p.kx_top, p.kx_fm) : (K)0;
+    if (HASV) vals[j] = idx < n ? (srcv ? srcv[bstart + idx] : (u32)(vgen + idx)) : 0u;
   }
   for (int pass = 0; pass < D; ++pass) {
     const u32 shift = pass * RADIX_BITS;

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_splitters(Plan p) {
   if (x >= p.B * per) return;
   const u32 b = x / per, k = x % per + 1;
   const u64 a = p.samp_start[b * p.P], S = p.samp_start[(b + 1) * p.P] - a;
-  K v = 0;
+  K v = key_in<K>((K)0, p.ky_top, p.ky_fm);  // no samples: the key type's zero
   if (S > 0) {
     const u64 r = ((u64)k * S) / p.P + p.P / 2 - 1;
     v = ((const K*)p.pool)[a + (r < S - 1 ? r : S - 1)];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_select_splitters(Plan p) {
   const u32 r = lane % F;
   const u64 a0 = p.samp_start[b * p.P];
   const u64 S = p.samp_start[(b + 1) * p.P] - a0;
-  K v = 0;
+  K v = key_in<K>((K)0, p.ky_top, p.ky_fm);  // no samples: the key type's zero
   if (S > 0) {
     const u64 t0 = ((u64)k * S) / p.P + p.P / 2 - 1;
     const u64 t = t0 < S - 1 ? t0 : S - 1;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_investigate(Plan p, u64* __restrict__ 
   if (out_cuts)
     for (u32 x = threadIdx.x; x < P * (P + 1); x += blockDim.x) out_cuts[(u64)b * P * (P + 1) + x] = cuts[x];
   if (out_split)
-    for (u32 x = threadIdx.x; x < per; x += blockDim.x) out_split[(u64)b * per + x] = v[x];
+    for (u32 x = threadIdx.x; x < per; x += blockDim.x) out_split[(u64)b * per + x] = key_out<K>(v[x], p.ky_top, p.ky_fm);
 }
 
 // ----------------------------------------------------------------- launchers

@@ -104,6 +104,13 @@ struct Plan {
   u64* grp_out;          // [NGmax][2]    per group: output offset, length
   u32 ng_max;            // merge groups, worst case over levels
   u32 mtiles_max;        // merge tiles, worst case over levels
+  // Keys of signed and floating-point types are sorted as unsigned integers
+  // through an order-preserving map (key_in), undone where keys leave the
+  // library (key_out).  Both are zero (the identity) except in the plan
+  // copies of the launches that read the caller's keys or write them back.
+  u64 kx_top, kx_fm;     // map applied to keys read from keys_in
+  u64 ky_top, ky_fm;     // inverse applied to keys written to keys_out / splitters
+  u32 vidx;              // values are generated: input position inside the instance
 };
 
 // ----------------------------------------------------------------- helpers
@@ -119,6 +126,27 @@ struct KeyT<u64> {
   static constexpr int BITS = 64;
   static constexpr u64 MAXV = ~0ull;
 };
+
+// The order-preserving map of a key type onto unsigned integers of the same
+// width: x ^ (top | (sign mask of x & fm)).  Unsigned: top = fm = 0.  Two's
+// complement: top = sign bit, fm = 0 (the sign bit flipped).  IEEE binary
+// floats: top = sign bit, fm = all other bits, so non-negative numbers get
+// their sign bit set and negative ones are complemented; unsigned order of the
+// images is then IEEE 754 totalOrder.  key_out inverts it: the sign of the
+// image decides which of the two cases the key came from.
+template <typename K>
+__device__ inline K sign_mask(K x) {
+  if constexpr (sizeof(K) == 8) return (K)((int64_t)x >> 63);
+  else return (K)((int32_t)x >> 31);
+}
+template <typename K>
+__device__ inline K key_in(K x, u64 top, u64 fm) {
+  return x ^ ((K)top | (sign_mask<K>(x) & (K)fm));
+}
+template <typename K>
+__device__ inline K key_out(K y, u64 top, u64 fm) {
+  return y ^ ((K)top | (sign_mask<K>((K)~y) & (K)fm));
+}
 
 __device__ inline u32 lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
 

@@ -369,3 +369,63 @@ def balance_keys_torch(dist: str, n: int, seed: int = 6, device="cuda", chunk: i
             raise ValueError(dist)
         out[a:e] = v
     return out.view(torch.uint64)
+
+
+# --------------------------------------------------------------------------
+# Signed and floating-point keys
+# --------------------------------------------------------------------------
+# Floats: Irwin-Hall of four uniforms (an approximately normal shape, like the
+# balance study's "normal"), centred and scaled: (u1 + u2 + u3 + u4 - 2) * 1000.
+# Only IEEE additions and multiplications in a fixed order, so host (numpy)
+# and device (torch) produce the same bits.  Every SPECIAL_EVERY-th key is one
+# of SPECIALS in turn (NaNs of both signs, infinities, signed zeros).
+SPECIAL_EVERY = 9973
+SPECIALS_F64 = (0x7FF8000000000000, 0xFFF8000000000000, 0x7FF0000000000000, 0xFFF0000000000000,
+                0x0000000000000000, 0x8000000000000000)
+
+
+def _specials(dtype) -> np.ndarray:
+    b = np.array(SPECIALS_F64, dtype=np.uint64).view(np.float64)
+    return b.astype(dtype) if dtype == np.float32 else b
+
+
+def typed_keys(n: int, seed: int, dtype, start: int = 0) -> np.ndarray:
+    """n keys of dtype (int32, int64, float32 or float64): signed integers are
+    uniform bit patterns; floats as described above."""
+    i = np.arange(start, start + n, dtype=np.uint64)
+    if dtype in (np.int64, np.int32):
+        k = u64(seed, i)
+        return (k >> np.uint64(32)).astype(np.uint32).view(np.int32) if dtype == np.int32 else k.view(np.int64)
+    acc = unit_double(u64(seed + 1000, i))
+    for j in range(1, 4):
+        acc = acc + unit_double(u64(seed + 1000 * (j + 1), i))
+    x = ((acc - 2.0) * 1000.0).astype(dtype)
+    sp = (i % np.uint64(SPECIAL_EVERY)) == 0
+    x[sp] = _specials(dtype)[(i[sp] // np.uint64(SPECIAL_EVERY)) % np.uint64(6)]
+    return x
+
+
+def typed_keys_torch(n: int, seed: int, dtype, device="cuda", chunk: int = 1 << 25):
+    """typed_keys(n, seed, dtype) generated on the device, bit for bit."""
+    import torch
+    tdt = {np.int32: torch.int32, np.int64: torch.int64, np.float32: torch.float32,
+           np.float64: torch.float64}[dtype]
+    out = torch.empty(n, dtype=tdt, device=device)
+    sp64 = torch.tensor(np.array(SPECIALS_F64, dtype=np.uint64).view(np.int64), device=device).view(torch.float64)
+    sp = sp64.to(tdt) if dtype == np.float32 else sp64
+    scale = 1.0 / 9007199254740992.0
+    for a in range(0, n, chunk):
+        e = min(n, a + chunk)
+        if dtype in (np.int64, np.int32):
+            k = u64_torch(seed, a, e - a, device).view(torch.int64)
+            out[a:e] = _lsr(k, 32).to(torch.int32) if dtype == np.int32 else k
+            continue
+        acc = _lsr(u64_torch(seed + 1000, a, e - a, device).view(torch.int64), 11).double() * scale
+        for j in range(1, 4):
+            acc = acc + _lsr(u64_torch(seed + 1000 * (j + 1), a, e - a, device).view(torch.int64), 11).double() * scale
+        x = ((acc - 2.0) * 1000.0).to(tdt)
+        idx = torch.arange(a, e, dtype=torch.int64, device=device)
+        m = (idx % SPECIAL_EVERY) == 0
+        x[m] = sp[(idx[m] // SPECIAL_EVERY) % 6]
+        out[a:e] = x
+    return out

@@ -18,8 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # compiled for comparison); by default the in-tree build is used.
 LIB_PATH = os.environ.get("LBSORT_LIB") or os.path.join(HERE, "_lib", "liblbsort.so")
 
-U32, U64 = 1, 2
-NOVAL, VAL_U32 = 0, 1
+U32, U64, I32, I64, F32, F64 = 1, 2, 3, 4, 5, 6
+NOVAL, VAL_U32, VAL_INDEX = 0, 1, 2
 INV_COUNT, INV_NONE, INV_PAPER = 0, 1, 2
 OK = 0
 ERR_INVALID_ARG, ERR_WORKSPACE_TOO_SMALL, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_DEVICE = -1, -2, -3, -4, -5, -6
@@ -40,7 +40,8 @@ class Parts(ctypes.Structure):
 
 EXPORTS = ("lbsort_sort_keys", "lbsort_sort_pairs", "lbsort_sort_batch", "lbsort_local_sort",
            "lbsort_check", "lbsort_status_string", "lbsort_last_error", "lbsort_autotune",
-           "lbsort_load_tuning", "lbsort_profile_enable", "lbsort_profile_read")
+           "lbsort_load_tuning", "lbsort_profile_enable", "lbsort_profile_read", "lbsort_search",
+           "lbsort_provenance")
 
 _lib = None
 
@@ -73,6 +74,8 @@ def load(path: str = LIB_PATH):
     lib.lbsort_load_tuning.argtypes = [ctypes.c_char_p]
     lib.lbsort_profile_enable.argtypes = [i32]
     lib.lbsort_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    lib.lbsort_search.argtypes = [i32, vp, u64, vp, u64, i32, vp, u32, vp, vp, vp]
+    lib.lbsort_provenance.argtypes = [vp, u64, u64, u32, vp, vp, vp]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.lbsort_status_string.restype = ctypes.c_char_p
@@ -95,12 +98,14 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+_KEY_CODES = {torch.uint32: U32, torch.uint64: U64, torch.int32: I32, torch.int64: I64,
+              torch.float32: F32, torch.float64: F64}
+
+
 def key_code(dtype) -> int:
-    if dtype == torch.uint64:
-        return U64
-    if dtype == torch.uint32:
-        return U32
-    raise TypeError(f"keys must be torch.uint64 or torch.uint32, got {dtype}")
+    if dtype in _KEY_CODES:
+        return _KEY_CODES[dtype]
+    raise TypeError(f"keys must be 32- or 64-bit unsigned, signed or float tensors, got {dtype}")
 
 
 @dataclass
@@ -158,18 +163,20 @@ def _run(fn, args_before_ws, ws: Workspace | None, device):
 def sort_batch(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torch.Tensor | None = None,
                s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0,
                keys_out=None, vals_out=None, want_send=False, want_cuts=False,
-               workspace: Workspace | None = None) -> SortResult:
-    """lbsort_sort_batch: seg_offsets is a device tensor of B+1 offsets (int64/uint64)."""
+               workspace: Workspace | None = None, index_values: bool = False) -> SortResult:
+    """lbsort_sort_batch: seg_offsets is a device tensor of B+1 offsets (int64/uint64).
+    index_values=True (with vals=None) sorts with LBSORT_VAL_INDEX."""
     lib = load()
     kc = key_code(keys.dtype)
     B = seg_offsets.numel() - 1
     n = keys.numel()
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
-    if vals is not None and vals_out is None:
-        vals_out = torch.empty_like(vals)
+    if (vals is not None or index_values) and vals_out is None:
+        vals_out = torch.empty(n, dtype=torch.uint32, device=keys.device)
+    vt = VAL_U32 if vals is not None else (VAL_INDEX if index_values else NOVAL)
     parts, offs, counts, spl, send, cuts = _alloc_parts(B, P, keys.dtype, keys.device, want_send, want_cuts)
     prm = _params(P, s, investigator, fanin, merge_tile)
-    args = (kc, VAL_U32 if vals is not None else NOVAL, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
+    args = (kc, vt, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
             _ptr(seg_offsets), B, n, ctypes.byref(prm), ctypes.byref(parts))
     buf = _run(lib.lbsort_sort_batch, args, workspace, keys.device)
     return SortResult(keys_out, vals_out, offs, counts, spl, send, cuts, buf)
@@ -189,20 +196,22 @@ def sort_keys(keys: torch.Tensor, P: int, s: int = 0, investigator: int = INV_CO
     return SortResult(keys_out, None, offs, counts, spl, send, cuts, buf)
 
 
-def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, P: int, s: int = 0, investigator: int = INV_COUNT,
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor | None, P: int, s: int = 0, investigator: int = INV_COUNT,
                fanin: int = 0, merge_tile: int = 0, keys_out=None, vals_out=None, want_send=False,
                want_cuts=False, workspace: Workspace | None = None) -> SortResult:
-    """lbsort_sort_pairs on one array of keys with uint32 values."""
+    """lbsort_sort_pairs on one array of keys with uint32 values.  vals=None
+    sorts with LBSORT_VAL_INDEX: vals_out receives every key's input position."""
     lib = load()
     kc = key_code(keys.dtype)
-    if vals.dtype != torch.uint32 or vals.numel() != keys.numel():
+    if vals is not None and (vals.dtype != torch.uint32 or vals.numel() != keys.numel()):
         raise TypeError("vals must be torch.uint32 with one value per key")
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
-    vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+    if vals_out is None:
+        vals_out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
     parts, offs, counts, spl, send, cuts = _alloc_parts(1, P, keys.dtype, keys.device, want_send, want_cuts)
     prm = _params(P, s, investigator, fanin, merge_tile)
-    args = (kc, VAL_U32, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), keys.numel(), ctypes.byref(prm),
-            ctypes.byref(parts))
+    args = (kc, VAL_U32 if vals is not None else VAL_INDEX, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
+            keys.numel(), ctypes.byref(prm), ctypes.byref(parts))
     buf = _run(lib.lbsort_sort_pairs, args, workspace, keys.device)
     return SortResult(keys_out, vals_out, offs, counts, spl, send, cuts, buf)
 
@@ -220,6 +229,40 @@ def local_sort(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torc
             _ptr(seg_offsets), B, keys.numel(), ctypes.byref(prm))
     buf = _run(lib.lbsort_local_sort, args, workspace, keys.device)
     return keys_out, vals_out, buf
+
+
+def search(sorted_keys: torch.Tensor, queries: torch.Tensor, upper: bool = False,
+           part_offsets: torch.Tensor | None = None):
+    """lbsort_search: positions of the queries in sorted_keys (number of keys
+    below, or not above, each query) and, with part_offsets ([P+1] device),
+    the partition holding each position (P past the end)."""
+    lib = load()
+    kc = key_code(sorted_keys.dtype)
+    if queries.dtype != sorted_keys.dtype:
+        raise TypeError("queries must have the dtype of sorted_keys")
+    nq = queries.numel()
+    pos = torch.empty(nq, dtype=torch.int64, device=queries.device)
+    part = None
+    P = 0
+    if part_offsets is not None:
+        P = part_offsets.numel() - 1
+        part = torch.empty(nq, dtype=torch.uint32, device=queries.device)
+    _check(lib.lbsort_search(kc, _ptr(sorted_keys), sorted_keys.numel(), _ptr(queries), nq, 1 if upper else 0,
+                             _ptr(part_offsets), P, _ptr(pos), _ptr(part), _stream()))
+    return pos, part
+
+
+def provenance(src_index: torch.Tensor, n: int, P: int):
+    """lbsort_provenance: block (processor) and offset inside it of every
+    input position in src_index (uint32), for n keys over P blocks."""
+    lib = load()
+    if src_index.dtype != torch.uint32:
+        raise TypeError("src_index must be torch.uint32")
+    cnt = src_index.numel()
+    blk = torch.empty(cnt, dtype=torch.uint32, device=src_index.device)
+    off = torch.empty(cnt, dtype=torch.uint32, device=src_index.device)
+    _check(lib.lbsort_provenance(_ptr(src_index), cnt, n, P, _ptr(blk), _ptr(off), _stream()))
+    return blk, off
 
 
 def check(workspace_buf: torch.Tensor):

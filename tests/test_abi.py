@@ -101,3 +101,40 @@ def test_missing_required_outputs(lib):
     rc = lib.lbsort_sort_keys(L.U64, None, None, 100, ctypes.byref(prm), None, ctypes.c_void_p(1 << 30),
                               ctypes.byref(big), None)
     assert rc == L.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("signed,unsigned", [(L.I64, L.U64), (L.F64, L.U64), (L.I32, L.U32), (L.F32, L.U32)])
+def test_typed_keys_share_the_unsigned_layout(lib, signed, unsigned):
+    for n in (0, 1000, 1 << 20):
+        rc_a, a = _size(key_type=signed, n=n)
+        rc_b, b = _size(key_type=unsigned, n=n)
+        assert rc_a == 0 and rc_b == 0 and a == b
+
+
+def test_index_values_need_32bit_positions(lib):
+    prm = L.Params(1, 0, 0, 0, 0, 0)
+    parts = L.Parts(1, 0, 0, 0, 0)
+    need = ctypes.c_size_t(0)
+    rc = lib.lbsort_sort_pairs(L.U64, L.VAL_INDEX, None, None, None, None, (1 << 32) + 1, ctypes.byref(prm),
+                               ctypes.byref(parts), None, ctypes.byref(need), None)
+    assert rc == L.ERR_UNSUPPORTED
+    rc = lib.lbsort_sort_pairs(L.U64, L.VAL_INDEX, None, None, None, None, 1 << 20, ctypes.byref(prm),
+                               ctypes.byref(parts), None, ctypes.byref(need), None)
+    assert rc == 0 and need.value > 0
+    rc = lib.lbsort_sort_pairs(L.U64, 3, None, None, None, None, 10, ctypes.byref(prm), ctypes.byref(parts), None,
+                               ctypes.byref(need), None)
+    assert rc == L.ERR_INVALID_ARG
+
+
+def test_search_and_provenance_argument_checks(lib):
+    p = ctypes.c_void_p(1 << 20)
+    # nothing to do: no device work, success
+    assert lib.lbsort_search(L.U64, None, 0, None, 0, 0, None, 0, None, None, None) == 0
+    assert lib.lbsort_provenance(None, 0, 10, 4, None, None, None) == 0
+    assert lib.lbsort_search(7, p, 10, p, 5, 0, None, 0, p, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_search(L.U64, p, 10, p, 5, 2, None, 0, p, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_search(L.U64, p, 10, None, 5, 0, None, 0, p, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_search(L.U64, p, 10, p, 5, 0, None, 4, p, p, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_provenance(p, 5, 10, 0, p, p, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_provenance(p, 5, (1 << 32) + 1, 4, p, p, None) == L.ERR_UNSUPPORTED
+    assert lib.lbsort_provenance(p, 5, 10, 4, None, None, None) == L.ERR_INVALID_ARG

@@ -46,3 +46,18 @@ def test_balance_shapes():
     # Irwin-Hall of four uniforms on [0, 2^62): mean 2^63, sd 2^62 / sqrt(3)
     assert abs(m.mean() / 2 ** 63 - 1) < 0.01
     assert abs(m.std() / (2 ** 62 / np.sqrt(3)) - 1) < 0.02
+
+
+@pytest.mark.parametrize("dt", [np.int32, np.int64, np.float32, np.float64])
+def test_typed_keys_host_and_device_generators_agree(dt):
+    a = G.typed_keys(60000, 7, dt)
+    b = G.typed_keys_torch(60000, 7, dt, device="cpu", chunk=25000).numpy()
+    assert a.dtype == dt and np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    tail = G.typed_keys(30000, 7, dt, start=30000)
+    assert np.array_equal(tail.view(np.uint8), a[30000:].view(np.uint8))
+    if np.issubdtype(dt, np.floating):
+        sp = a[::G.SPECIAL_EVERY]
+        assert np.isnan(sp[0]) and np.isnan(sp[1]) and np.signbit(sp[1]) and sp[2] == np.inf and sp[3] == -np.inf
+        assert sp[4] == 0 and not np.signbit(sp[4]) and sp[5] == 0 and np.signbit(sp[5])
+        fin = np.delete(a, np.arange(0, len(a), G.SPECIAL_EVERY))
+        assert np.all(np.abs(fin) <= 2000.0)
