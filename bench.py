@@ -36,6 +36,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KEY_NAMES = {"torch.uint64": "u64", "torch.uint32": "u32", "torch.int64": "i64", "torch.int32": "i32",
+             "torch.float64": "f64", "torch.float32": "f32"}
 KERNEL_SOURCE = {"onesweep": "kernels_radix.hip", "merge": "kernels_merge.hip"}
 METRIC = "GKeys/s sorted (u64) + max/mean partition imbalance; batched vs per-instance"
 
@@ -48,6 +50,13 @@ WORKLOADS = {
                  gen="dups", seed=3, tag="dups_2e28"),
     "keys1m": dict(desc="plain sort: 1,048,576 uniform u64 keys, P=8, 16 regular samples per block, keys only",
                    n=1 << 20, P=8, s=16, vals=False, gen="uniform", seed=1, tag="keys1m"),
+    "f64": dict(desc="float keys with provenance: 268,435,456 IEEE binary64 keys (Irwin-Hall of four uniforms, "
+                     "centred, x1000; every 9973rd a NaN, infinity or signed zero), generated u32 index values, "
+                     "P=64, 512 regular samples per block", n=1 << 28, P=64, s=512, vals="index", gen="typed",
+                dtype="float64", seed=21, tag="f64_2e28"),
+    "i64": dict(desc="signed keys with provenance: 268,435,456 uniform int64 keys, generated u32 index values, "
+                     "P=64, 512 regular samples per block", n=1 << 28, P=64, s=512, vals="index", gen="typed",
+                dtype="int64", seed=21, tag="i64_2e28"),
 }
 
 
@@ -95,14 +104,17 @@ def profile_read(lib):
 
 
 def make_input(w, device):
+    import numpy as np
     import torch
     from paper_1611_00463_amd import datagen
     n = w["n"]
     if w["gen"] == "uniform":
         keys = datagen.uniform_keys_torch(n, w["seed"], device)
+    elif w["gen"] == "typed":
+        keys = datagen.typed_keys_torch(n, w["seed"], getattr(np, w["dtype"]), device)
     else:
         keys = torch.from_numpy(datagen.duplicate_heavy_keys(n, seed=w["seed"])).to(device)
-    vals = datagen.index_values_torch(n, device) if w["vals"] else None
+    vals = datagen.index_values_torch(n, device) if w["vals"] is True else None
     return keys, vals
 
 
@@ -111,13 +123,16 @@ def cpu_baseline(w, sample_n):
     import numpy as np
     from oracle import sample_sort as O
     from paper_1611_00463_amd import datagen
+    from oracle import typed as T
     if w["gen"] == "uniform":
         keys = datagen.uniform_keys(sample_n, seed=w["seed"])
+    elif w["gen"] == "typed":
+        keys = datagen.typed_keys(sample_n, seed=w["seed"], dtype=getattr(np, w["dtype"]))
     else:
         keys = datagen.duplicate_heavy_keys(sample_n, seed=w["seed"])
     vals = datagen.index_values(sample_n) if w["vals"] else None
     t0 = time.perf_counter()
-    O.sample_sort(keys, vals, w["P"], w["s"], O.INV_COUNT)
+    T.sample_sort_typed(keys, vals, w["P"], w["s"], O.INV_COUNT)
     dt = time.perf_counter() - t0
     return {"value": round(sample_n / dt / 1e9, 6), "unit": "GKeys/s", "cores": 1, "kind": "oracle",
             "sample": f"first {sample_n} keys of the same workload (same P and s), numpy oracle, one thread, "
@@ -303,6 +318,77 @@ def bench_balance(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_search(args):
+    """Binary search over a sorted result (Section III, Section IV.C): 2^28
+    uniform u64 keys sorted once with P = 64 (untimed), then K timed calls of
+    lbsort_search for 2^24 queries (half of them keys of the data, half random
+    64-bit values), each returning the position and the holding partition."""
+    import numpy as np
+    import torch
+    from paper_1611_00463_amd import datagen
+    from paper_1611_00463_amd import lbsort as L
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    lib = L.load()
+    n, P, nq = 1 << 28, 64, 1 << 24
+    print(f"[bench] search: sorting {n} keys, {nq} queries", file=sys.stderr, flush=True)
+    keys = datagen.uniform_keys_torch(n, 2, dev)
+    r = L.sort_keys(keys, P, s=512)
+    L.check(r.workspace)
+    sk, G = r.keys, r.part_offsets[0].contiguous()
+    del keys
+    pick = datagen.u64_torch(40, 0, nq // 2, dev).view(torch.int64).remainder(n)
+    q = torch.cat([sk.view(torch.int64)[pick], datagen.u64_torch(41, 0, nq - nq // 2, dev).view(torch.int64)])
+    pos = torch.empty(nq, dtype=torch.int64, device=dev)
+    part = torch.empty(nq, dtype=torch.uint32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rc = lib.lbsort_search(L.U64, L._ptr(sk), n, L._ptr(q), nq, 0, L._ptr(G), P, L._ptr(pos), L._ptr(part),
+                               L._stream())
+        if rc:
+            raise RuntimeError(f"lbsort_search failed: {rc}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lib.lbsort_profile_enable(1)
+    profile_read(lib)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lib.lbsort_profile_enable(0)
+    prof = profile_read(lib)
+    ms = e0.elapsed_time(e1) / args.steps
+    # spot check against the data itself: sk[pos-1] < q <= sk[pos]
+    idx = torch.arange(0, nq, 9973, device=dev)
+    pp, qq = pos[idx], q[idx]
+    sgn = -(1 << 63)
+    sv, qv = sk.view(torch.int64) ^ sgn, qq.view(torch.int64) ^ sgn
+    ok_lo = (pp == 0) | (sv[(pp - 1).clamp(min=0)] < qv)
+    ok_hi = (pp == n) | (sv[pp.clamp(max=n - 1)] >= qv)
+    assert bool((ok_lo & ok_hi).all()), "search positions inconsistent with the sorted data"
+    c, t = prof["search"]
+    per = nq * (8 + 8 + 4)                    # query in, position and partition out
+    achieved = per / (t / c / 1e3) / 1e9
+    line = {
+        "metric": "GQueries/s, binary search over sorted u64 keys", "value": round(nq / (ms / 1e3) / 1e9, 4),
+        "unit": "GQueries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "search: 16,777,216 queries (half keys of the data, half random) over 268,435,456 "
+                               "sorted uniform u64 keys in 64 partitions", "n": n, "queries": nq, "P": P},
+        "roofline": {"kernel": "search", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "bytes_per_launch": per, "avg_launch_ms": round(t / c, 5),
+                     "note": "about 28 dependent loads per query: latency-bound, the byte figure counts only "
+                             "the query and its two outputs"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_serve(args):
     """Served form: a Poisson stream of u64 sort requests (sizes log-uniform in
     [10K, 64M], uniform / Zipf(1.2) / sorted / reverse keys sliced from 64M-key
@@ -352,7 +438,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch", "serve", "balance"])
+    ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch", "serve", "balance", "search"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--fanin", type=int, default=0)
@@ -388,6 +474,8 @@ def main():
         return bench_serve(args)
     if args.workload == "balance":
         return bench_balance(args)
+    if args.workload == "search":
+        return bench_search(args)
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -395,12 +483,13 @@ def main():
     print(f"[bench] generating {w['n']} keys ({args.workload})", file=sys.stderr, flush=True)
     keys, vals = make_input(w, dev)
     kout = torch.empty_like(keys)
-    vout = torch.empty_like(vals) if vals is not None else None
+    has_v = bool(w["vals"])
+    vout = torch.empty(w["n"], dtype=torch.uint32, device=dev) if has_v else None
     ws = L.Workspace(dev)
-    kb, vb = 8, 4 if vals is not None else 0
+    kb, vb = keys.element_size(), 4 if has_v else 0
 
     def step():
-        if vals is None:
+        if not has_v:
             return L.sort_keys(keys, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
                                keys_out=kout, workspace=ws)
         return L.sort_pairs(keys, vals, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
@@ -448,9 +537,10 @@ def main():
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": w["desc"], "n": n, "P": w["P"], "s": w["s"], "key": "u64",
-                   "value": "u32" if vals is not None else None, "investigator": "COUNT",
+        "vs_baseline": None, "dtype": KEY_NAMES[str(keys.dtype)], "data": "synthetic",
+        "config": {"workload": w["desc"], "n": n, "P": w["P"], "s": w["s"], "key": KEY_NAMES[str(keys.dtype)],
+                   "value": {True: "u32", "index": "u32 index (generated)", False: None}[w["vals"]],
+                   "investigator": "COUNT",
                    "fanin": args.fanin or "tuned", "merge_tile": args.merge_tile or "tuned"},
         "imbalance": imb,
         "roofline": roof,

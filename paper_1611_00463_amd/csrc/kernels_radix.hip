@@ -452,18 +452,28 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
 
       K keys[ITEMS];
       u32 vals[HASV ? ITEMS : 1];
-      // without a value array the values are the keys' input positions
-      // inside their instance
-      const u64 vgen = HASV && srcv == nullptr ? tbase - p.seg[blk / p.P] : 0;
+      if (!HASV || srcv != nullptr) {
 #pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        const u32 idx = wbase + j * 64 + lane;
-        if (idx < tile_n) {
-          keys[j] = src[tbase + idx];
-          if (HASV) vals[j] = srcv ? srcv[tbase + idx] : (u32)(vgen + idx);
-        } else {
-          keys[j] = 0;
-          if (HASV) vals[j] = 0;
+        for (int j = 0; j < ITEMS; ++j) {
+          const u32 idx = wbase + j * 64 + lane;
+          if (idx < tile_n) {
+            keys[j] = src[tbase + idx];
+            if (HASV) vals[j] = srcv[tbase + idx];
+          } else {
+            keys[j] = 0;
+            if (HASV) vals[j] = 0;
+          }
+        }
+      } else {
+        // no value array: the values are the keys' input positions inside
+        // their instance (a separate loop, so that the key loads stay in
+        // flight together)
+        const u64 vgen = tbase - p.seg[blk / p.P];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+          const u32 idx = wbase + j * 64 + lane;
+          keys[j] = idx < tile_n ? src[tbase + idx] : (K)0;
+          if (HASV) vals[j] = (u32)(vgen + idx);
         }
       }
       if ((p.kx_top | p.kx_fm) != 0) {
@@ -733,12 +743,26 @@ __global__ __launch_bounds__(SORT_NT) void k_small_sort(Plan p, const K* __restr
   const u32 wbase = w * WI;
   K keys[SORT_ITEMS];
   u32 vals[HASV ? SORT_ITEMS : 1];
-  const u64 vgen = HASV && srcv == nullptr ? bstart - p.seg[blk / p.P] : 0;
+  if (!HASV || srcv != nullptr) {
 #pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const u32 idx = wbase + j * 64 + lane;
-    keys[j] = idx < n ? key_in<K>(src[bstart + idx], p.kx_top, p.kx_fm) : (K)0;
-    if (HASV) vals[j] = idx < n ? (srcv ? srcv[bstart + idx] : (u32)(vgen + idx)) : 0u;
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const u32 idx = wbase + j * 64 + lane;
+      keys[j] = idx < n ? src[bstart + idx] : (K)0;
+      if (HASV) vals[j] = idx < n ? srcv[bstart + idx] : 0u;
+    }
+  } else {
+    // no value array: the values are the keys' input positions inside their instance
+    const u64 vgen = bstart - p.seg[blk / p.P];
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const u32 idx = wbase + j * 64 + lane;
+      keys[j] = idx < n ? src[bstart + idx] : (K)0;
+      if (HASV) vals[j] = (u32)(vgen + idx);
+    }
+  }
+  if ((p.kx_top | p.kx_fm) != 0) {
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) keys[j] = key_in<K>(keys[j], p.kx_top, p.kx_fm);
   }
   for (int pass = 0; pass < D; ++pass) {
     const u32 shift = pass * RADIX_BITS;
