@@ -25,6 +25,10 @@ template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s);
 template <bool HASV>
 void launch_group_fix(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s);
+template <bool HASV>
+void launch_group_fix_mid(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s);
+template <bool HASV>
+void launch_group_mid(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, u32 wgs, hipStream_t s);
 template <typename K>
 void launch_split(const Plan& p, const K* sorted, u64 max_samples, const void* out_offsets, void* out_counts,
                   void* out_send, void* out_cuts, void* out_split, hipStream_t s);
@@ -116,9 +120,15 @@ struct Shape {
 };
 
 struct Layout {
-  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, tdesc, gflags, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
+  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, tdesc, gflags, gflags2, midlist, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
       splitters, mtile, rec_start, rec_end, rec_out, rec_n, slot_grp, grp_run, grp_out, tmpk, tmpv, seg, total;
 };
+
+// Entries of the mid-size group list: groups of more than GF_HALO keys in the
+// large blocks of 64-bit keys.
+static u64 mid_cap(const Shape& sh) {
+  return key_width(sh.key_type) == 8 && sh.has_large ? sh.total_n / (GF_HALO + 1) + 1 : 0;
+}
 
 static Layout make_layout(const Shape& sh) {
   Layout l;
@@ -141,6 +151,8 @@ static Layout make_layout(const Shape& sh) {
   l.status = take(sh.max_tiles * RADIX * 8);
   l.tdesc = take(sh.max_tiles * sizeof(TileDesc));
   l.gflags = take(NB * 4);
+  l.gflags2 = take(NB * 4);
+  l.midlist = take(mid_cap(sh) * 8);
   l.samples = take(sh.max_samples * K);
   l.pool = take(sh.max_samples * K);
   l.lo = take(B * P * (P - 1) * 8);
@@ -271,6 +283,9 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.rem_prefix = (u32*)(ws + lay.rem_prefix);
   p.tdesc = (TileDesc*)(ws + lay.tdesc);
   p.gflags = (u32*)(ws + lay.gflags);
+  p.gflags2 = (u32*)(ws + lay.gflags2);
+  p.midlist = (u64*)(ws + lay.midlist);
+  p.mid_cap = mid_cap(sh);
   p.counters = (u32*)(ws + lay.counters);
   p.hist = (u32*)(ws + lay.hist);
   p.status = (u64*)(ws + lay.status);
@@ -337,12 +352,15 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         K* const O = F == kout ? tk : kout;
         u32* const OV = HASV ? (FV == vout ? tv : vout) : nullptr;
         launch_fill32(p.gflags, p.NB, 0, st);
+        launch_fill32(p.gflags2, p.NB, 0, st);
         launch_onesweep<K, HASV>(px, kin, vin, O, OV, 5, st);
         launch_onesweep<K, HASV>(p, O, OV, F, FV, 6, st);
         launch_onesweep<K, HASV>(p, F, FV, O, OV, 7, st);
         launch_group_fix<HASV>(p, (const u64*)O, OV, (u64*)F, FV, st);
+        launch_group_fix_mid<HASV>(p, (const u64*)O, OV, (u64*)F, FV, st);
+        launch_group_mid<HASV>(p, (const u64*)O, OV, (u64*)F, FV, device_cus() * 8, st);
         Plan q = p;
-        q.only = p.gflags;
+        q.only = p.gflags2;
         q.epoch_base = 8;  // the status words of the passes above stay valid for epochs 6..8
         launch_fill32(p.counters + C_TICKET, NQ * sh.D, 0, st);
         launch_plan(q, st);

@@ -340,10 +340,11 @@ __global__ __launch_bounds__(256) void k_scan_hist(Plan p) {
 // wave keeps the ranking stable.  wc: this wave's 256 digit counters.
 template <typename K, int ITEMS, typename C>
 __device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n, u32 shift, C* wc,
-                                  u32 (&rank)[ITEMS], u32 (&dig)[ITEMS]) {
+                                  u32 (&rank)[ITEMS], u32 (&dig)[ITEMS], int nj = ITEMS) {
   const u32 lane = threadIdx.x & 63;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
+    if (j >= nj) break;  // items past a wave-uniform count hold no keys
     const bool valid = wbase + j * 64 + lane < tile_n;
     const u32 d = (u32)(keys[j] >> shift) & (RADIX - 1);
     // Peers: lanes whose digit equals this lane's.  For every digit bit the
@@ -610,8 +611,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
 //    the number of group members before it in (key, position) order;
 //  * a larger group keeps its order, which is right when all its keys are
 //    equal (heavy duplicates); a key of it that differs from its predecessor
-//    flags the block, which is then sorted again over all eight digits.
-constexpr u32 GF_HALO = 64;
+//    flags the block for k_group_fix_mid.
 constexpr u32 GF_SHIFT = 40;
 constexpr int GF_NT = 1024;
 constexpr u32 GF_WIN = SORT_TILE + 2 * GF_HALO;
@@ -720,6 +720,389 @@ void launch_group_fix(const Plan& p, const u64* src, const u32* srcv, u64* dst, 
 }
 template void launch_group_fix<false>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
 template void launch_group_fix<true>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
+
+// ----------------------------------------------------------------- mid-size group fix-up
+// The fix-up again, for the blocks k_group_fix flagged (a group of more than
+// GF_HALO keys with different keys).  One workgroup per tile of such a block.
+// It holds the tile and GF_HALO keys on either side in LDS, and marks group
+// starts over a wider window of GF_MID keys on either side (from the top bits
+// alone), so that every group of at most GF_MID keys that touches the tile is
+// seen whole:
+//  * a group of at most GF_HALO keys: each key's place is the group start
+//    plus the number of group members before it in (key, position) order;
+//  * a group of GF_HALO+1 .. GF_MID keys is listed (by the tile holding its
+//    first key) for k_group_mid, which sorts it in LDS and writes it;
+//  * a larger group keeps its order, which is right when all its keys are
+//    equal (heavy duplicates); a key of it that differs from its predecessor
+//    flags the block again (gflags2), which is then sorted over all eight
+//    digits.
+constexpr u32 GF_XWIN = SORT_TILE + 2 * GF_MID;
+
+template <bool HASV>
+__global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __restrict__ src,
+                                                    const u32* __restrict__ srcv, u64* __restrict__ dst,
+                                                    u32* __restrict__ dstv) {
+  constexpr u32 NW = GF_XWIN / 64 + 2;      // head-bit words, with room for the block's end
+  constexpr u32 XH = GF_MID - GF_HALO;      // outer halo: top bits only
+  __shared__ u64 s_k[GF_WIN + 1];           // keys of the tile and the inner halo (+ one spill slot)
+  __shared__ u32 s_xt[2][XH];               // top bits of the outer halo, left and right
+  __shared__ u64 s_hb[NW];                  // bit x: window position x starts a group
+  __shared__ u32 s_last[NW];                // last group start in words <= w (or none)
+  __shared__ u32 s_first[NW];               // first group start in words >= w (or none)
+  __shared__ u64 s_mid[GF_MIDPT];  // mid-size groups starting in the tile
+  __shared__ u32 s_nmid, s_mbase, s_empty;
+  __shared__ u32 s_blk;
+  const u32 tid = threadIdx.x, lane = tid & 63;
+  const u32 t = blockIdx.x;
+  if (t >= p.tstart[p.NB]) return;
+  if (tid == 0) {
+    s_blk = find_seg(p.tstart, p.NB, t);
+    s_nmid = 0;
+    s_empty = 0;
+  }
+  for (u32 i = tid; i < NW; i += GF_NT) s_hb[i] = 0;
+  __syncthreads();
+  const u32 blk = s_blk;
+  if (p.gflags[blk] == 0) return;  // the first fix-up finished this block
+  const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
+  const u64 ts = bs + (u64)(t - p.tstart[blk]) * SORT_TILE;
+  const u64 te = be - ts < (u64)SORT_TILE ? be : ts + SORT_TILE;
+  // inner window [ws, we) in LDS
+  const u64 ws = ts - bs > GF_HALO ? ts - GF_HALO : bs;
+  const u64 we = be - te > GF_HALO ? te + GF_HALO : be;
+  const u32 wn = (u32)(we - ws);
+  // all loads issued at once: the inner window's keys (into LDS) and this
+  // thread's values of the tile (kept in registers until the write)
+  constexpr int KL = (GF_WIN + GF_NT - 1) / GF_NT, VL = SORT_TILE / GF_NT;
+  const u32 o0 = (u32)(ts - ws), o1 = (u32)(te - ws);
+  u32 v[HASV ? VL : 1];
+  if (HASV) {
+#pragma unroll
+    for (int k = 0; k < VL; ++k) {
+      const u32 w = o0 + (u32)k * GF_NT + tid;
+      v[k] = w < o1 ? srcv[ws + w] : 0u;
+    }
+  }
+  {
+    u64 kk[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const u32 i = (u32)k * GF_NT + tid;
+      kk[k] = src[ws + (i < wn ? i : wn - 1)];  // clamped, not predicated: all loads in flight together
+    }
+    // positions past wn take clamped copies, which nothing reads; those past
+    // the array go to its spill slot (no predicated store, so that no load
+    // is moved behind the wait of the others)
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const u32 i = (u32)k * GF_NT + tid;
+      s_k[i < GF_WIN ? i : GF_WIN] = kk[k];
+    }
+  }
+  __syncthreads();
+  // The outer window [xs, xe) reaches GF_MID keys past the tile on a side
+  // only where the group at that edge of the tile runs to the edge of the
+  // inner window (equal top bits there, since the keys are sorted by them);
+  // elsewhere every group touching the tile starts and ends inside.
+  const bool need_l = ws > bs && (s_k[0] >> GF_SHIFT) == (s_k[o0] >> GF_SHIFT);
+  const bool need_r = we < be && (s_k[wn - 1] >> GF_SHIFT) == (s_k[o1 - 1] >> GF_SHIFT);
+  const u64 xs = need_l ? (ts - bs > GF_MID ? ts - GF_MID : bs) : ws;
+  const u64 xe = need_r ? (be - te > GF_MID ? te + GF_MID : be) : we;
+  const u32 xn = (u32)(xe - xs);
+  const u32 nl = (u32)(ws - xs), nr = (u32)(xe - we);  // outer halo lengths (<= XH)
+  if (need_l || need_r) {
+    // top bits of the outer halo: one position per thread and side
+    static_assert(XH <= (u32)GF_NT, "one outer-halo position per thread");
+    const u32* const hi = reinterpret_cast<const u32*>(src) + 1;  // high words: hi[2 g]
+    if (tid < nl) s_xt[0][tid] = hi[2 * (xs + tid)] >> (GF_SHIFT - 32);
+    if (tid < nr) s_xt[1][tid] = hi[2 * (we + tid)] >> (GF_SHIFT - 32);
+    __syncthreads();
+  }
+  // top bits of outer-window position x
+  auto top = [&](u32 x) -> u32 {
+    if (x < nl) return s_xt[0][x];
+    const u32 i = x - nl;
+    return i < wn ? (u32)(s_k[i] >> GF_SHIFT) : s_xt[1][i - wn];
+  };
+  // Position x starts a group when it is the block's first key or its top
+  // bits differ from those at x - 1; the window's first position inside a
+  // block is no start (a group reaching past it counts as too large), and the
+  // block's end counts as one.  One ballot per 64 positions.
+  // A word inside the window without any start (a run of 64 equal top bits)
+  // is noted: only then can a group's bounds lie beyond the neighbouring
+  // words.  (The window's last, partial word holds position xn, whose start
+  // bit is set at the block's end; otherwise a group reaching it is too large
+  // either way.)
+  const bool xfirst = xs == bs, xlast = xe == be;
+  if (nl == 0 && nr == 0) {
+    for (u32 base = 0; base < xn + 1; base += GF_NT) {
+      const u32 x = base + tid;
+      bool h = false;
+      if (x < xn) h = x == 0 ? xfirst : (s_k[x] >> GF_SHIFT) != (s_k[x - 1] >> GF_SHIFT);
+      else if (x == xn) h = xlast;
+      const u64 m = __ballot(h);
+      if (lane == 0 && x < xn + 64) {
+        s_hb[x >> 6] = m;
+        if (m == 0 && x + 64 <= xn) s_empty = 1u;  // a whole word inside the window
+      }
+    }
+  } else {
+    for (u32 base = 0; base < xn + 1; base += GF_NT) {
+      const u32 x = base + tid;
+      bool h = false;
+      if (x < xn) h = x == 0 ? xfirst : top(x) != top(x - 1);
+      else if (x == xn) h = xlast;
+      const u64 m = __ballot(h);
+      if (lane == 0 && x < xn + 64) {
+        s_hb[x >> 6] = m;
+        if (m == 0 && x + 64 <= xn) s_empty = 1u;  // a whole word inside the window
+      }
+    }
+  }
+  __syncthreads();
+  // Nearest group starts per word, when some word has none: a running
+  // maximum from the left and a running minimum from the right, by the
+  // first wave (three words per lane).
+  constexpr u32 NONE = 0xFFFFFFFFu;
+  static_assert(NW <= 3 * 64, "three head-bit words per lane");
+  const bool tables = s_empty != 0;
+  if (tables && tid < 64) {
+    u32 last[3], first[3];
+    u32 run = 0;  // last start + 1 (0: none)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const u32 wi = tid * 3 + i;
+      const u64 m = wi < NW ? s_hb[wi] : 0;
+      if (m) run = wi * 64 + 64 - (u32)__clzll((long long)m);
+      last[i] = run;
+    }
+    u32 incl = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const u32 y = __shfl_up(incl, d);
+      if (tid >= (u32)d && y > incl) incl = y;
+    }
+    u32 prev = __shfl_up(incl, 1);
+    if (tid == 0) prev = 0;
+    u32 runf = NONE;  // first start
+#pragma unroll
+    for (int i = 2; i >= 0; --i) {
+      const u32 wi = tid * 3 + i;
+      const u64 m = wi < NW ? s_hb[wi] : 0;
+      if (m) runf = wi * 64 + (u32)__ffsll((long long)m) - 1;
+      first[i] = runf;
+    }
+    u32 inclf = runf;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const u32 y = __shfl_down(inclf, d);
+      if (tid + d < 64 && y < inclf) inclf = y;
+    }
+    u32 nextf = __shfl_down(inclf, 1);
+    if (tid == 63) nextf = NONE;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const u32 wi = tid * 3 + i;
+      if (wi < NW) {
+        const u32 l = last[i] > prev ? last[i] : prev;
+        s_last[wi] = l ? l - 1 : NONE;
+        s_first[wi] = first[i] < nextf ? first[i] : nextf;
+      }
+    }
+  }
+  if (tables) __syncthreads();
+  // Places first (mid-size group starts gathered in LDS), then one list
+  // reservation per tile, then the writes.
+  bool bad = false;
+  u32 place[VL];  // outer-window output position, NONE for a mid-size group's key
+#pragma unroll
+  for (int k = 0; k < VL; ++k) {
+    place[k] = NONE;
+    const u32 w = o0 + (u32)k * GF_NT + tid;  // inner-window position
+    if (w >= o1) break;
+    const u32 x = w + nl;                      // outer-window position
+    const u64 key = s_k[w];
+    // group bounds: the last start at or before x and the first start after it
+    const u32 xi = x >> 6, b = x & 63;
+    const u64 upto = ((u64)2 << b) - 1;  // bits 0..b
+    const u64 hb = s_hb[xi];
+    const u64 mb = hb & upto, ma = hb & ~upto;
+    u32 gs = NONE, ge = NONE;
+    if (mb) {
+      gs = xi * 64 + 63 - (u32)__clzll((long long)mb);
+    } else if (xi > 0) {
+      const u64 m = s_hb[xi - 1];  // not empty unless the tables were built
+      gs = m ? (xi - 1) * 64 + 63 - (u32)__clzll((long long)m) : (tables ? s_last[xi - 1] : NONE);
+    }
+    if (ma) {
+      ge = xi * 64 + (u32)__ffsll((long long)ma) - 1;
+    } else if (xi + 1 < NW) {
+      const u64 m = s_hb[xi + 1];
+      ge = m ? (xi + 1) * 64 + (u32)__ffsll((long long)m) - 1 : (tables ? s_first[xi + 1] : NONE);
+    }
+    const bool whole = gs != NONE && ge != NONE && ge <= xn;
+    const u32 gn = whole ? ge - gs : 0xFFFFFFFFu;
+    u32 o = x;
+    if (gn <= GF_HALO) {
+      // inside the inner window: rank among the group by (key, position)
+      u32 r = 0;
+      for (u32 j = gs - nl; j < ge - nl; ++j) {
+        const u64 kj = s_k[j];
+        r += (kj < key || (kj == key && j < w)) ? 1u : 0u;
+      }
+      o = gs + r;
+    } else if (gn > GF_MID && gs != x && s_k[w - 1] != key) {
+      bad = true;  // a large group with different keys (w >= 1 here)
+    }
+    if (gn > GF_HALO && gn <= GF_MID) {
+      // written by k_group_mid; listed once, by the tile holding its start
+      if (x == gs) s_mid[atomicAdd(&s_nmid, 1u)] = (xs + gs) | ((u64)gn << 44);
+    } else {
+      place[k] = o;
+    }
+  }
+  __syncthreads();
+  const u32 nm = s_nmid;
+  if (nm) {
+    if (tid == 0) s_mbase = atomicAdd(&p.counters[C_NMID], nm);
+    __syncthreads();
+    const u32 base = s_mbase;
+    for (u32 i = tid; i < nm; i += GF_NT) {
+      if ((u64)base + i < p.mid_cap) p.midlist[base + i] = s_mid[i];
+      else bad = true;  // cannot happen for a list of n / (GF_HALO + 1) + 1 entries; the block is redone
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < VL; ++k) {
+    const u32 w = o0 + (u32)k * GF_NT + tid;
+    if (w >= o1) break;
+    if (place[k] != NONE) {
+      dst[xs + place[k]] = s_k[w];
+      if (HASV) dstv[xs + place[k]] = v[k];
+    }
+  }
+  if (bad) p.gflags2[blk] = 1u;
+}
+
+template <bool HASV>
+void launch_group_fix_mid(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s) {
+  if (p.max_tiles == 0) return;
+  const int pe_ = prof_begin(s);
+  hipLaunchKernelGGL(k_group_fix_mid<HASV>, dim3(p.max_tiles), dim3(GF_NT), 0, s, p, src, srcv, dst, dstv);
+  prof_end(pe_, "group_fix_mid", s);
+}
+template void launch_group_fix_mid<false>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
+template void launch_group_fix_mid<true>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
+
+// ----------------------------------------------------------------- mid-size groups
+// Groups of GF_HALO+1 .. GF_MID keys listed by k_group_fix.  Their top 24 bits
+// are equal, so a stable LSD sort over the five low digits finishes them.
+// Each wave takes whole groups (static stride over the list): the group sits
+// in registers (GM_ITEMS keys per lane), every pass ranks with the wave's own
+// digit counters and scatters through the wave's LDS slice.
+constexpr int GM_NT = 256;
+constexpr int GM_WAVES = GM_NT / 64;
+constexpr int GM_ITEMS = GF_MID / 64;
+constexpr int GM_DIGITS = GF_SHIFT / RADIX_BITS;
+
+// LDS accesses of one wave to its own slice, ordered across its lanes.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool HASV>
+__global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restrict__ src,
+                                                    const u32* __restrict__ srcv, u64* __restrict__ dst,
+                                                    u32* __restrict__ dstv) {
+  __shared__ u64 s_k[GM_WAVES][GF_MID];
+  __shared__ u32 s_v[GM_WAVES][HASV ? GF_MID : 1];
+  __shared__ u32 s_c[GM_WAVES][RADIX];
+  const u32 lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const u64 nmid = p.counters[C_NMID] < p.mid_cap ? p.counters[C_NMID] : p.mid_cap;
+  const u32 nw = gridDim.x * GM_WAVES;
+  u64* const sk = s_k[w];
+  u32* const sv = s_v[w];
+  u32* const sc = s_c[w];
+  for (u64 e = blockIdx.x * GM_WAVES + w; e < nmid; e += nw) {
+    const u64 ent = p.midlist[e];
+    const u64 g0 = ent & ((1ull << 44) - 1);
+    const u32 len = (u32)(ent >> 44) < GF_MID ? (u32)(ent >> 44) : GF_MID;
+    const int nj = (int)((len + 63) / 64);
+    u64 keys[GM_ITEMS];
+    u32 vals[HASV ? GM_ITEMS : 1];
+#pragma unroll
+    for (int j = 0; j < GM_ITEMS; ++j) {
+      const u32 idx = j * 64 + lane;
+      keys[j] = idx < len ? src[g0 + idx] : 0;
+      if (HASV) vals[j] = idx < len ? srcv[g0 + idx] : 0u;
+    }
+    for (u32 pass = 0; pass < GM_DIGITS; ++pass) {
+      for (u32 i = lane; i < RADIX; i += 64) sc[i] = 0;
+      wave_lds_sync();
+      u32 rank[GM_ITEMS], dig[GM_ITEMS];
+      rank_items<u64, GM_ITEMS, u32>(keys, 0, len, pass * RADIX_BITS, sc, rank, dig, nj);
+      wave_lds_sync();
+      // every key has the same digit: the pass leaves the order as it is
+      if (sc[__shfl(dig[0], 0)] == len) continue;
+      // exclusive scan of the 256 counts, four per lane
+      const u32 c0 = sc[4 * lane], c1 = sc[4 * lane + 1], c2 = sc[4 * lane + 2], c3 = sc[4 * lane + 3];
+      const u32 tsum = c0 + c1 + c2 + c3;
+      u32 incl = tsum;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const u32 y = __shfl_up(incl, d);
+        if (lane >= (u32)d) incl += y;
+      }
+      const u32 ex = incl - tsum;
+      wave_lds_sync();
+      sc[4 * lane] = ex;
+      sc[4 * lane + 1] = ex + c0;
+      sc[4 * lane + 2] = ex + c0 + c1;
+      sc[4 * lane + 3] = ex + c0 + c1 + c2;
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < GM_ITEMS; ++j) {
+        if (j >= nj) break;
+        if (j * 64 + lane < len) {
+          const u32 pos = sc[dig[j]] + rank[j];
+          sk[pos] = keys[j];
+          if (HASV) sv[pos] = vals[j];
+        }
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < GM_ITEMS; ++j) {
+        if (j >= nj) break;
+        const u32 idx = j * 64 + lane;
+        if (idx < len) {
+          keys[j] = sk[idx];
+          if (HASV) vals[j] = sv[idx];
+        }
+      }
+      wave_lds_sync();
+    }
+#pragma unroll
+    for (int j = 0; j < GM_ITEMS; ++j) {
+      const u32 idx = j * 64 + lane;
+      if (idx < len) {
+        dst[g0 + idx] = keys[j];
+        if (HASV) dstv[g0 + idx] = vals[j];
+      }
+    }
+  }
+}
+
+template <bool HASV>
+void launch_group_mid(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, u32 wgs, hipStream_t s) {
+  if (p.max_tiles == 0 || p.mid_cap == 0) return;
+  const int pe_ = prof_begin(s);
+  hipLaunchKernelGGL(k_group_mid<HASV>, dim3(wgs), dim3(GM_NT), 0, s, p, src, srcv, dst, dstv);
+  prof_end(pe_, "group_mid", s);
+}
+template void launch_group_mid<false>(const Plan&, const u64*, const u32*, u64*, u32*, u32, hipStream_t);
+template void launch_group_mid<true>(const Plan&, const u64*, const u32*, u64*, u32*, u32, hipStream_t);
 
 // ----------------------------------------------------------------- small blocks
 // A block of at most one tile is sorted entirely in LDS: all digit passes,

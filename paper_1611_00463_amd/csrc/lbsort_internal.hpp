@@ -23,6 +23,13 @@ constexpr int SORT_ITEMS = 16;
 constexpr int SMALL_TILE = SORT_NT * SORT_ITEMS;  // 4096 keys
 constexpr int SORT_TILE = LBS_RADIX_TILE;
 constexpr int WAVE = 64;
+// Group fix-up of the 64-bit local sort: groups of at most GF_HALO keys are
+// ranked in place; in the blocks that have larger groups of different keys,
+// groups of up to GF_MID keys are listed (at most n / (GF_HALO + 1) of them)
+// and sorted by a second kernel.
+constexpr u32 GF_HALO = 64;
+constexpr u32 GF_MID = 512;
+constexpr u32 GF_MIDPT = SORT_TILE / (GF_HALO + 1) + 1;  // listed groups starting in one radix tile, at most
 
 // Look-back status word: [63:56] epoch (pass + 1), [55:54] flag, [53:0] count.
 constexpr u64 ST_AGG = 1, ST_INC = 2;
@@ -37,6 +44,7 @@ enum Counter : int {
   C_ERR = 0,        // device error bits (sticky until lbsort_check)
   C_NSMALL = 1,     // number of blocks sorted whole in LDS
   C_NLARGE = 2,     // blocks larger than one tile
+  C_NMID = 3,       // groups listed for the mid-size group sort
   C_QPARAM = 8,     // C_QPARAM + 4x + {0: blocks, 1: rmin, 2: first status slot, 3: tiles} of queue x
   C_TICKET = 64,    // C_TICKET + NQ * pass + x: next ticket of queue x in radix pass `pass`
   C_COUNT = 128
@@ -82,6 +90,9 @@ struct Plan {
   const u32* only;       // [NB] or null: plan only the large blocks with only[b] != 0
   u32 epoch_base;        // added to the look-back epochs of the radix passes
   u32* gflags;           // [NB] blocks the group fix-up could not finish
+  u32* gflags2;          // [NB] blocks the mid-size group fix-up could not finish either
+  u64* midlist;          // [mid_cap] groups of 65..GF_MID keys: start | length << 44
+  u64 mid_cap;           // entries of midlist (0: no list)
   u32* counters;         // [C_COUNT]
   u32* hist;             // [NB][D][256]
   u64* status;           // [max_tiles][256]

@@ -147,7 +147,7 @@ def _top_small_keys(n, seed, top_values):
     return (np.asarray(top_values, dtype=np.uint64)[pick] << np.uint64(40)) | low
 
 
-@pytest.mark.parametrize("case", ["all_below_2_40", "half_blocks", "medium_groups", "small_groups"])
+@pytest.mark.parametrize("case", ["all_below_2_40", "half_blocks", "medium_groups", "small_groups", "clustered_f64"])
 def test_local_sort_group_paths(ws, case):
     n, P = 1_000_000, 8
     if case == "all_below_2_40":          # one group per block with distinct keys: every block falls back
@@ -155,12 +155,54 @@ def test_local_sort_group_paths(ws, case):
     elif case == "half_blocks":           # blocks 0-3 fall back, blocks 4-7 take the fix-up
         keys = datagen.uniform_keys(n, seed=42)
         keys[: n // 2] >>= np.uint64(24)
-    elif case == "medium_groups":         # 1000 top values: groups of ~125 keys per block
+    elif case == "medium_groups":         # 1000 top values: groups of ~125 keys per block (mid-size sort)
         keys = _top_small_keys(n, 43, list(range(7, 7007, 7)))
-    else:                                  # 2^16 top values: groups of a few keys, many straddling tiles
+    elif case == "small_groups":          # 2^16 top values: groups of a few keys, many straddling tiles
         keys = _top_small_keys(n, 44, list(range(0, 1 << 16)))
+    else:                                  # normal-like doubles as unsigned images: groups of up to ~300 keys
+        n, P = 4_000_000, 2
+        x = datagen.typed_keys(n, seed=47, dtype=np.float64).view(np.uint64)
+        keys = np.where(x >> np.uint64(63) == 1, ~x, x | np.uint64(1 << 63))
     vals = datagen.index_values(n)
     check_case(keys, vals, P, 0, ws=ws)
+
+
+def _sized_groups_block(rng, n_target, sizes, seed):
+    """Keys of one block made of groups (equal top 24 bits) of the given sizes,
+    in random order: groups of different keys, and now and then a group whose
+    keys are all equal."""
+    parts, gid, total = [], 1, 0
+    while total < n_target:
+        g = int(sizes[rng.integers(0, len(sizes))])
+        low = datagen.uniform_keys(g, seed=seed + gid) >> np.uint64(24)
+        if rng.random() < 0.15:
+            low[:] = low[0]                       # all keys of the group equal
+        parts.append((np.uint64(gid * 37 + 5) << np.uint64(40)) | low)
+        gid += 1
+        total += g
+    keys = np.concatenate(parts)
+    return keys[rng.permutation(len(keys))]
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_group_sizes_at_the_thresholds(ws, P):
+    """Groups of every size class of the 64-bit fix-up at once, ranked in
+    place (<= 64 keys), sorted by the mid-size kernel (65..512) or left for
+    the eight-pass sort (> 512 different keys), straddling tiles and blocks."""
+    rng = np.random.default_rng(46 + P)
+    sizes = [1, 2, 63, 64, 65, 66, 200, 511, 512, 513, 900, 5000]
+    blocks = [_sized_groups_block(rng, 300_000, sizes, 1000 * (b + 1)) for b in range(P)]
+    # equal block sizes, so that block i is exactly the i-th part
+    m = min(len(b) for b in blocks)
+    keys = np.concatenate([b[:m] for b in blocks])
+    check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws)
+    # the same groups but no group above 512 keys: no block falls back
+    sizes = [1, 64, 65, 100, 300, 512]
+    blocks = [_sized_groups_block(rng, 300_000, sizes, 5000 * (b + 1)) for b in range(P)]
+    m = min(len(b) for b in blocks)
+    keys = np.concatenate([b[:m] for b in blocks])
+    check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws)
+    check_case(keys, None, P, 0, ws=ws)
 
 
 def test_local_sort_paths_agree(ws, monkeypatch):
