@@ -69,3 +69,32 @@ def test_duplicate_heavy_full_size():
     plan = check_metadata(r, keys_np)
     counts = plan["part_counts"]
     assert counts.max() / counts.mean() <= 1.05, "investigator lost the balance"
+
+
+def test_f64_index_values_full_size():
+    """2^28 normal-like doubles with NaNs, infinities and signed zeros, and
+    generated index values: the float workload of bench.py.  Most blocks take
+    the mid-size group fix-up.  Partition metadata against the oracle (on the
+    keys' totalOrder integers); the output by properties that pin it: keys
+    in totalOrder, index values a permutation, each output key the input key
+    at its index, equal keys in increasing index order."""
+    from oracle import typed as T
+    keys = datagen.typed_keys_torch(N, 21, np.float64, "cuda")
+    r = L.sort_pairs(keys, None, P, s=S, want_send=True, want_cuts=True)
+    L.check(r.workspace)
+    bits = r.keys.view(torch.int64)
+    # totalOrder as a signed integer: negative patterns reversed
+    tko = torch.where(bits < 0, bits ^ 0x7FFFFFFFFFFFFFFF, bits)
+    assert bool((tko[1:] >= tko[:-1]).all()), "keys not in totalOrder"
+    vo = r.vals.view(torch.int32).to(torch.int64)
+    assert bool((torch.bincount(vo, minlength=N) == 1).all()), "index values are not a permutation"
+    assert bool((bits == keys.view(torch.int64)[vo]).all()), "an output key is not the input key at its index"
+    eq = tko[1:] == tko[:-1]
+    assert bool((vo[1:][eq] > vo[:-1][eq]).all()), "not stable"
+    del tko, vo, eq, bits
+    keys_np = keys.cpu().numpy()
+    plan = O.partition_plan(T.total_order_int(keys_np), P, S)
+    assert_same("splitters", T.total_order_int(r.splitters.cpu().numpy()[0]), plan["splitters"])
+    assert_same("cuts", u64(r.cuts)[0], plan["cuts"].astype(np.uint64))
+    assert_same("send_counts", u64(r.send_counts)[0], plan["send_counts"].astype(np.uint64))
+    assert_same("part_offsets", u64(r.part_offsets)[0], plan["part_offsets"].astype(np.uint64))
