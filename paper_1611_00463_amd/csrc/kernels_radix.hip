@@ -708,7 +708,11 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restri
     dst[ws + o] = key;
     if (HASV) dstv[ws + o] = v[k];
   }
-  if (bad) p.gflags[blk] = 1u;
+  // one store per wave that found a mixed large group
+  if (__ballot(bad) != 0 && lane == 0) {
+    p.gflags[blk] = 1u;
+    p.counters[C_ANYFLAG] = 1u;
+  }
 }
 
 template <bool HASV>
@@ -754,7 +758,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
   __shared__ u32 s_blk;
   const u32 tid = threadIdx.x, lane = tid & 63;
   const u32 t = blockIdx.x;
-  if (t >= p.tstart[p.NB]) return;
+  if (p.counters[C_ANYFLAG] == 0 || t >= p.tstart[p.NB]) return;  // no block flagged
   if (tid == 0) {
     s_blk = find_seg(p.tstart, p.NB, t);
     s_nmid = 0;
@@ -981,7 +985,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
       if (HASV) dstv[xs + place[k]] = v[k];
     }
   }
-  if (bad) p.gflags2[blk] = 1u;
+  if (__ballot(bad) != 0 && lane == 0) p.gflags2[blk] = 1u;
 }
 
 template <bool HASV>

@@ -45,6 +45,7 @@ enum Counter : int {
   C_NSMALL = 1,     // number of blocks sorted whole in LDS
   C_NLARGE = 2,     // blocks larger than one tile
   C_NMID = 3,       // groups listed for the mid-size group sort
+  C_ANYFLAG = 4,    // some block was flagged by the group fix-up
   C_QPARAM = 8,     // C_QPARAM + 4x + {0: blocks, 1: rmin, 2: first status slot, 3: tiles} of queue x
   C_TICKET = 64,    // C_TICKET + NQ * pass + x: next ticket of queue x in radix pass `pass`
   C_COUNT = 128
