@@ -46,40 +46,6 @@ __device__ inline u64 block_exclusive_scan(u64 v, u64* s_w, u64& total) {
   return wprefix + x - v;
 }
 
-// Exclusive running extreme over the workgroup's threads of small signed
-// values: FROM_LEFT gives the max over threads < tid (identity -1), otherwise
-// the min over threads > tid (identity INT_MAX).
-template <int NT, bool FROM_LEFT>
-__device__ inline int block_exclusive_extreme(int v, int* s_w) {
-  constexpr int NWV = NT / 64;
-  constexpr int ID = FROM_LEFT ? -1 : 0x7FFFFFFF;
-  const u32 lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    if (FROM_LEFT) {
-      const int y = __shfl_up(x, o);
-      if (lane >= (u32)o) x = x > y ? x : y;
-    } else {
-      const int y = __shfl_down(x, o);
-      if (lane + o < 64) x = x < y ? x : y;
-    }
-  }
-  int ex = FROM_LEFT ? __shfl_up(x, 1) : __shfl_down(x, 1);
-  if (FROM_LEFT ? lane == 0 : lane == 63) ex = ID;
-  if (FROM_LEFT ? lane == 63 : lane == 0) s_w[w] = x;
-  __syncthreads();
-  int c = ID;
-  for (int q = 0; q < NWV; ++q) {
-    if (FROM_LEFT ? (u32)q < w : (u32)q > w) {
-      const int y = s_w[q];
-      c = FROM_LEFT ? (c > y ? c : y) : (c < y ? c : y);
-    }
-  }
-  __syncthreads();
-  return FROM_LEFT ? (c > ex ? c : ex) : (c < ex ? c : ex);
-}
-
 // ----------------------------------------------------------------- plan
 // One workgroup: block starts, radix tile prefix, list of blocks small enough
 // to be sorted whole in LDS, and sample offsets, for every block of every
@@ -1023,12 +989,14 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
   __shared__ u64 s_k[GM_WAVES][GF_MID];
   __shared__ u32 s_v[GM_WAVES][HASV ? GF_MID : 1];
   __shared__ u32 s_c[GM_WAVES][RADIX];
+  __shared__ u64 s_hw[GM_WAVES][GM_ITEMS + 1];  // run-start bits of a group
   const u32 lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const u64 nmid = p.counters[C_NMID] < p.mid_cap ? p.counters[C_NMID] : p.mid_cap;
   const u32 nw = gridDim.x * GM_WAVES;
   u64* const sk = s_k[w];
   u32* const sv = s_v[w];
   u32* const sc = s_c[w];
+  u64* const shw = s_hw[w];
   for (u64 e = blockIdx.x * GM_WAVES + w; e < nmid; e += nw) {
     const u64 ent = p.midlist[e];
     const u64 g0 = ent & ((1ull << 44) - 1);
@@ -1042,14 +1010,16 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
       keys[j] = idx < len ? src[g0 + idx] : 0;
       if (HASV) vals[j] = idx < len ? srcv[g0 + idx] : 0u;
     }
-    for (u32 pass = 0; pass < GM_DIGITS; ++pass) {
+    // One stable LSD pass over digit `pass` (scatter through the wave's LDS
+    // slice); left out when every key has the same digit there.
+    auto radix_pass = [&](u32 pass) {
       for (u32 i = lane; i < RADIX; i += 64) sc[i] = 0;
       wave_lds_sync();
       u32 rank[GM_ITEMS], dig[GM_ITEMS];
       rank_items<u64, GM_ITEMS, u32>(keys, 0, len, pass * RADIX_BITS, sc, rank, dig, nj);
       wave_lds_sync();
       // every key has the same digit: the pass leaves the order as it is
-      if (sc[__shfl(dig[0], 0)] == len) continue;
+      if (sc[__shfl(dig[0], 0)] == len) return;
       // exclusive scan of the 256 counts, four per lane
       const u32 c0 = sc[4 * lane], c1 = sc[4 * lane + 1], c2 = sc[4 * lane + 2], c3 = sc[4 * lane + 3];
       const u32 tsum = c0 + c1 + c2 + c3;
@@ -1086,6 +1056,70 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
         }
       }
       wave_lds_sync();
+    };
+    // The top 24 bits are equal in a group.  One pass over digit 4 (bits
+    // 32..39) leaves runs of keys with equal bits 32..63, short for keys
+    // spread over the low 40 bits; a run of at most 64 keys is finished by
+    // ranking by (key, position).  If some run is longer, the five passes over
+    // digits 0..4 sort the group instead (stable from any starting order).
+    radix_pass(GM_DIGITS - 1);
+#pragma unroll
+    for (int j = 0; j < GM_ITEMS; ++j) {
+      if (j >= nj) break;
+      const u32 idx = j * 64 + lane;
+      if (idx < len) sk[idx] = keys[j];
+    }
+    wave_lds_sync();
+    // run starts (and the end at len), one ballot per 64 positions
+#pragma unroll
+    for (int j = 0; j <= GM_ITEMS; ++j) {
+      if (j > nj) break;
+      const u32 i = j * 64 + lane;
+      const bool h = i < len ? (i == 0 || (sk[i] >> 32) != (sk[i - 1] >> 32)) : i == len;
+      const u64 m = __ballot(h);
+      if (lane == 0) shw[j] = m;
+    }
+    wave_lds_sync();
+    u32 run[GM_ITEMS];  // run start | run end << 16
+    bool longrun = false;
+#pragma unroll
+    for (int j = 0; j < GM_ITEMS; ++j) {
+      run[j] = 0;
+      if (j >= nj) break;
+      const u32 i = j * 64 + lane;
+      if (i < len) {
+        const u64 upto = ((u64)2 << lane) - 1;  // bits 0..lane
+        u64 m = shw[j] & upto;
+        int wi = j;
+        while (m == 0) m = shw[--wi];  // position 0 is a start
+        const u32 rs = (u32)wi * 64 + 63 - (u32)__clzll((long long)m);
+        m = shw[j] & ~upto;
+        wi = j;
+        while (m == 0) m = shw[++wi];  // position len is marked
+        const u32 re = (u32)wi * 64 + (u32)__ffsll((long long)m) - 1;
+        run[j] = rs | re << 16;
+        longrun = longrun || re - rs > 64;
+      }
+    }
+    if (__ballot(longrun) != 0) {
+      for (u32 pass = 0; pass < GM_DIGITS; ++pass) radix_pass(pass);
+    } else {
+#pragma unroll
+      for (int j = 0; j < GM_ITEMS; ++j) {
+        if (j >= nj) break;
+        const u32 i = j * 64 + lane;
+        if (i < len) {
+          const u32 rs = run[j] & 0xFFFFu, re = run[j] >> 16;
+          u32 r = rs;
+          for (u32 x = rs; x < re; ++x) {
+            const u64 kx = sk[x];
+            r += (kx < keys[j] || (kx == keys[j] && x < i)) ? 1u : 0u;
+          }
+          dst[g0 + r] = keys[j];
+          if (HASV) dstv[g0 + r] = vals[j];
+        }
+      }
+      continue;
     }
 #pragma unroll
     for (int j = 0; j < GM_ITEMS; ++j) {

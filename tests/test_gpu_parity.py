@@ -167,14 +167,14 @@ def test_local_sort_group_paths(ws, case):
     check_case(keys, vals, P, 0, ws=ws)
 
 
-def _sized_groups_block(rng, n_target, sizes, seed):
+def _sized_groups_block(rng, n_target, sizes, seed, low_bits=40):
     """Keys of one block made of groups (equal top 24 bits) of the given sizes,
-    in random order: groups of different keys, and now and then a group whose
-    keys are all equal."""
+    in random order: groups of different keys (random in their low `low_bits`
+    bits), and now and then a group whose keys are all equal."""
     parts, gid, total = [], 1, 0
     while total < n_target:
         g = int(sizes[rng.integers(0, len(sizes))])
-        low = datagen.uniform_keys(g, seed=seed + gid) >> np.uint64(24)
+        low = datagen.uniform_keys(g, seed=seed + gid) >> np.uint64(64 - low_bits)
         if rng.random() < 0.15:
             low[:] = low[0]                       # all keys of the group equal
         parts.append((np.uint64(gid * 37 + 5) << np.uint64(40)) | low)
@@ -203,6 +203,13 @@ def test_group_sizes_at_the_thresholds(ws, P):
     keys = np.concatenate([b[:m] for b in blocks])
     check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws)
     check_case(keys, None, P, 0, ws=ws)
+    # groups whose keys differ only in their low 32 bits (long runs after the
+    # first pass of the group sort) or only in their low 8 bits (many equal keys)
+    for low_bits in (32, 8):
+        blocks = [_sized_groups_block(rng, 200_000, sizes, 9000 * (b + 1), low_bits) for b in range(P)]
+        m = min(len(b) for b in blocks)
+        keys = np.concatenate([b[:m] for b in blocks])
+        check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws)
 
 
 def test_local_sort_paths_agree(ws, monkeypatch):
