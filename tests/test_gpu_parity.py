@@ -212,6 +212,31 @@ def test_group_sizes_at_the_thresholds(ws, P):
         check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws)
 
 
+def test_batch_with_group_paths(ws):
+    """A batch of 64-bit instances whose blocks take every branch of the local
+    sort's fix-up: small groups, listed mid-size groups, mixed groups above 512
+    keys (the eight-pass sort), and a uniform instance; P = 3 and 4."""
+    rng = np.random.default_rng(48)
+    parts = [
+        _sized_groups_block(rng, 200_000, [1, 64, 65, 300, 512], 11000),
+        datagen.uniform_keys(150_001, seed=49),
+        _sized_groups_block(rng, 120_000, [2, 100, 513, 5000], 12000),
+        np.zeros(0, dtype=np.uint64),
+        _sized_groups_block(rng, 90_000, [70, 200], 13000, low_bits=32),
+    ]
+    sizes = [len(k) for k in parts]
+    keys = np.concatenate(parts)
+    vals = np.concatenate([np.arange(n, dtype=np.uint32) for n in sizes])
+    seg = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    for P in (3, 4):
+        r = L.sort_batch(to_dev(keys), to_dev(seg), P, vals=to_dev(vals), s=64, want_send=True, want_cuts=True)
+        L.check(r.workspace)
+        for b in range(len(sizes)):
+            a, e = int(seg[b]), int(seg[b + 1])
+            o = O.sample_sort(keys[a:e], vals[a:e], P, 64)
+            compare(r, o, P, b=b, seg=(a, e))
+
+
 def test_local_sort_paths_agree(ws, monkeypatch):
     """The same bytes with the fix-up and with all eight radix passes."""
     keys = datagen.uniform_keys(1 << 21, seed=45)
