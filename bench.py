@@ -251,7 +251,8 @@ def bench_balance(args):
     distributions, sorted by P = 10 virtual processors with the sample budget
     X = 256 KB / P and with 0.004X ... 1.4X, under each investigator mode at X.
     Also min/max partition sizes for P = 8 ... 52 at 0.004X, X and 1.4X on
-    uniform keys.  value = the largest max/mean share over the four
+    uniform keys, and every distribution at P = 8 ... 52 with the default
+    budget (balance and sort rate: the paper's workload suite).  value = the largest max/mean share over the four
     distributions at X with the count-based investigator (Table 2's setting)."""
     import numpy as np
     import torch
@@ -273,7 +274,7 @@ def bench_balance(args):
         return {"max_over_mean": round(float(c.max() / c.mean()), 6), "min_pct": round(float(100 * c.min() / c.sum()), 4),
                 "max_pct": round(float(100 * c.max() / c.sum()), 4), "max_minus_min": int(c.max() - c.min())}
 
-    table2, sweep, modes_at_x, rates = {}, {}, {}, {}
+    table2, sweep, modes_at_x, rates, suite = {}, {}, {}, {}, {}
     X = 262144 // (P * 8)
     for dist in datagen.BALANCE_DISTS:
         print(f"[bench] balance: {dist}", file=sys.stderr, flush=True)
@@ -293,6 +294,16 @@ def bench_balance(args):
         e1.record()
         torch.cuda.synchronize()
         rates[dist] = round(n / (e0.elapsed_time(e1) / 3 / 1e3) / 1e9, 3)
+        # the workload suite: every distribution at P = 8 ... 52 with the
+        # default sample budget, balance and sort rate (one timed sort each)
+        suite[dist] = {}
+        for Pp in (8, 16, 32, 52):
+            c = shares(keys, Pp, 0, L.INV_COUNT)
+            e0.record()
+            L.sort_keys(keys, Pp, s=0, keys_out=kout, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            suite[dist][str(Pp)] = dict(GKeys_s=round(n / (e0.elapsed_time(e1) / 1e3) / 1e9, 3), **summary(c))
         del keys
     print("[bench] balance: processor sweep", file=sys.stderr, flush=True)
     keys = datagen.balance_keys_torch("uniform", n, device="cuda")
@@ -313,7 +324,7 @@ def bench_balance(args):
                                f"exponential), P=10, s = X = {X} and 0.004X..1.4X, COUNT/NONE/PAPER",
                    "n": n, "P": P, "X": X},
         "table2_shares_pct": table2, "sample_sweep": sweep, "modes_at_X": modes_at_x, "processor_sweep": procs,
-        "GKeys_s_at_X": rates,
+        "GKeys_s_at_X": rates, "suite_P8_to_52": suite,
     }
     print(json.dumps(line), flush=True)
 
