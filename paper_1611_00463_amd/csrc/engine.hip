@@ -16,6 +16,7 @@
 namespace lbs {
 
 void launch_plan(const Plan& p, hipStream_t s);
+void launch_redo_digits(const Plan& p, hipStream_t s);
 void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s);
 template <typename K>
 void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo = 0);
@@ -369,9 +370,15 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         qx.kx_fm = fm;
         launch_fill32(p.hist, (u64)p.NB * sh.D * RADIX, 0, st);
         launch_hist<K>(qx, kin, st);
-        for (u32 j = 0; j < sh.D; ++j)
-          launch_onesweep<K, HASV>(j ? q : qx, j ? (j % 2 ? O : F) : kin, j ? (j % 2 ? OV : FV) : vin, j % 2 ? F : O,
-                                   j % 2 ? FV : OV, j, st);
+        launch_redo_digits(q, st);
+        // only the digits that reorder some flagged block are passed over;
+        // the first pass that runs reads the input (and maps typed keys), the
+        // last writes F (the kernels pick their buffers from the digit mask)
+        qx.redo_out = F;
+        qx.redo_outv = FV;
+        qx.redo_tmp = O;
+        qx.redo_tmpv = OV;
+        for (u32 j = 0; j < sh.D; ++j) launch_onesweep<K, HASV>(qx, kin, vin, F, FV, j, st);
       } else {
         for (u32 j = 0; j < sh.D; ++j)
           launch_onesweep<K, HASV>(j ? p : px, j ? dk(j - 1) : kin, j ? dv(j - 1) : vin, dk(j), dv(j), j, st);

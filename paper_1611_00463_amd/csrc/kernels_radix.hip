@@ -265,9 +265,29 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
         }
         done = done || same;
       }
-      if (!done) {
+      // the rest, digit by digit.  Counting every digit (the fallback plan of
+      // 64-bit keys, 32-bit keys), a digit the remaining lanes share (a run
+      // of equal high bytes, as in clustered or small keys) is counted once;
+      // the top digits of the fix-up path count lane by lane (cheaper on
+      // spread keys, the common case there).
+      const u64 rest = __ballot(!done);
+      if (DLO > 0) {
+        if (!done) {
 #pragma unroll
-        for (int q = DLO; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1))], 1u);
+          for (int q = DLO; q < D; ++q) atomicAdd(&h[q * RADIX + (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1))], 1u);
+        }
+      } else if (rest) {
+        const int first = __ffsll((unsigned long long)rest) - 1;
+#pragma unroll
+        for (int q = DLO; q < D; ++q) {
+          const u32 d = (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1));
+          const u32 d0 = (u32)__shfl((int)d, first);
+          if (__ballot(!done && d != d0) == 0) {
+            if (lane == (u32)first) atomicAdd(&h[q * RADIX + d0], (u32)__popcll(rest));
+          } else if (!done) {
+            atomicAdd(&h[q * RADIX + d], 1u);
+          }
+        }
       }
     }
   }
@@ -342,12 +362,44 @@ __device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n,
 // A tile waits only for tiles of its own queue with smaller tickets, which
 // running workgroups hold, so the waits always end.
 // REDO: a pass of the fallback plan (blocks the group fix-up flagged); it is
-// a separate instantiation so that profiles tell the two apart, and it leaves
-// at once when the plan holds no block.
+// a separate instantiation so that profiles tell the two apart.  It leaves
+// at once when the plan holds no block or when the digit is the same for all
+// keys of each planned block (k_redo_digits); the passes that do run choose
+// their buffers so that the first reads the input (src0) and the last writes
+// the plan's output buffer.
+// The digit passes of the fallback plan that change any planned block's
+// order: bit j of C_REDO_DIGITS is set when some planned block has keys in
+// two or more buckets of digit j (a pass over a digit that is the same for
+// all keys of every block leaves every block as it is).  The histogram holds
+// block-relative exclusive bucket starts by now, so one bucket holds every
+// key exactly when every start is 0 or the block size.
+__global__ __launch_bounds__(1024) void k_redo_digits(Plan p) {
+  __shared__ u32 s_bits;
+  if (threadIdx.x == 0) s_bits = 0;
+  __syncthreads();
+  const u32 nl = p.counters[C_NLARGE];
+  for (u32 i = threadIdx.x; i < nl * p.D; i += 1024) {
+    const u32 blk = p.large_list[i / p.D], j = i % p.D;
+    const u32 nb = (u32)(p.blk_start[blk + 1] - p.blk_start[blk]);
+    const u32* const h = p.hist + ((u64)blk * p.D + j) * RADIX;
+    bool varies = false;
+    for (u32 d = 0; d < RADIX && !varies; ++d) varies = h[d] != 0 && h[d] != nb;
+    if (varies) atomicOr(&s_bits, 1u << j);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) p.counters[C_REDO_DIGITS] = s_bits;
+}
+
+void launch_redo_digits(const Plan& p, hipStream_t s) {
+  const int pe_ = prof_begin(s);
+  hipLaunchKernelGGL(k_redo_digits, dim3(1), dim3(1024), 0, s, p);
+  prof_end(pe_, "redo_digits", s);
+}
+
 template <typename K, bool HASV, int NT, int ITEMS, int MINW, bool REDO>
-__global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restrict__ src,
-                                                 const u32* __restrict__ srcv, K* __restrict__ dst,
-                                                 u32* __restrict__ dstv, u32 pass) {
+__global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restrict__ src0,
+                                                 const u32* __restrict__ srcv0, K* __restrict__ dst0,
+                                                 u32* __restrict__ dstv0, u32 pass) {
   constexpr int NWV = NT / 64, WI = 64 * ITEMS;
   static_assert(NT * ITEMS == SORT_TILE, "tiles of SORT_TILE keys");
   static_assert(NT >= RADIX, "one thread per digit");
@@ -384,7 +436,26 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
   const u32 shift = pass * RADIX_BITS;
   const u32 epoch = pass + 1 + p.epoch_base;
   const u32 nq = p.nq;
-  if (REDO && p.counters[C_NLARGE] == 0) return;
+  const K* src = src0;
+  const u32* srcv = srcv0;
+  K* dst = dst0;
+  u32* dstv = dstv0;
+  u64 kx_top = p.kx_top, kx_fm = p.kx_fm;  // applied to keys read from the input only
+  if (REDO) {
+    if (p.counters[C_NLARGE] == 0) return;
+    const u32 run = p.counters[C_REDO_DIGITS];  // bit j: pass j reorders some planned block
+    if (((run >> pass) & 1u) == 0) return;
+    const u32 a = (u32)__popc(run & ((1u << pass) - 1u)), e = (u32)__popc(run);
+    // executed pass k writes the output buffer when e - 1 - k is even
+    const bool to_out = ((e - 1u - a) & 1u) == 0;
+    dst = (K*)(to_out ? p.redo_out : p.redo_tmp);
+    dstv = (u32*)(to_out ? p.redo_outv : p.redo_tmpv);
+    if (a > 0) {
+      src = (const K*)(to_out ? p.redo_tmp : p.redo_out);
+      srcv = (const u32*)(to_out ? p.redo_tmpv : p.redo_outv);
+      kx_top = kx_fm = 0;
+    }
+  }
   for (u32 qi = 0; qi < nq; ++qi) {
     const u32 x = (blockIdx.x + qi) % nq;
     const TileQueue Q{x, nq, p.counters[C_QPARAM + 4 * x], p.counters[C_QPARAM + 4 * x + 1], p.rem_prefix};
@@ -443,9 +514,9 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
           if (HASV) vals[j] = (u32)(vgen + idx);
         }
       }
-      if ((p.kx_top | p.kx_fm) != 0) {
+      if ((kx_top | kx_fm) != 0) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) keys[j] = key_in<K>(keys[j], p.kx_top, p.kx_fm);
+        for (int j = 0; j < ITEMS; ++j) keys[j] = key_in<K>(keys[j], kx_top, kx_fm);
       }
       u32 rank[ITEMS];
       {

@@ -46,6 +46,7 @@ enum Counter : int {
   C_NLARGE = 2,     // blocks larger than one tile
   C_NMID = 3,       // groups listed for the mid-size group sort
   C_ANYFLAG = 4,    // some block was flagged by the group fix-up
+  C_REDO_DIGITS = 5,  // bit j: fallback pass j reorders some planned block
   C_QPARAM = 8,     // C_QPARAM + 4x + {0: blocks, 1: rmin, 2: first status slot, 3: tiles} of queue x
   C_TICKET = 64,    // C_TICKET + NQ * pass + x: next ticket of queue x in radix pass `pass`
   C_COUNT = 128
@@ -123,6 +124,12 @@ struct Plan {
   u64 kx_top, kx_fm;     // map applied to keys read from keys_in
   u64 ky_top, ky_fm;     // inverse applied to keys written to keys_out / splitters
   u32 vidx;              // values are generated: input position inside the instance
+  // Buffers of the fallback plan's passes (the passes that run alternate
+  // between them so that the last one writes redo_out).
+  void* redo_out;
+  u32* redo_outv;
+  void* redo_tmp;
+  u32* redo_tmpv;
 };
 
 // ----------------------------------------------------------------- helpers
