@@ -16,7 +16,6 @@
 namespace lbs {
 
 void launch_plan(const Plan& p, hipStream_t s);
-void launch_redo_digits(const Plan& p, hipStream_t s);
 void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s);
 template <typename K>
 void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo = 0);
@@ -340,7 +339,13 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   launch_plan(p, st);
   // the fix-up path of 64-bit keys needs the counts of the three top digits only
   const bool hybrid = sizeof(K) == 8 && hybrid_local_sort();
-  if (sh.has_large) launch_hist<K>(px, kin, st, hybrid ? 5u : 0u);
+  // the fix-up path's top-digit passes leave out a digit that no block needs
+  Plan ph = px;
+  if (hybrid) {
+    ph.run_slot = C_RUN_TOP;
+    ph.run_mask = 0xE0u;  // digits 5, 6, 7
+  }
+  if (sh.has_large) launch_hist<K>(hybrid ? ph : px, kin, st, hybrid ? 5u : 0u);
   if (sh.has_small) launch_small_sort<K, HASV>(px, kin, vin, dk(sh.D - 1), dv(sh.D - 1), st);
   if (sh.has_large) {
     if constexpr (sizeof(K) == 8) {
@@ -354,9 +359,12 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         u32* const OV = HASV ? (FV == vout ? tv : vout) : nullptr;
         launch_fill32(p.gflags, p.NB, 0, st);
         launch_fill32(p.gflags2, p.NB, 0, st);
-        launch_onesweep<K, HASV>(px, kin, vin, O, OV, 5, st);
-        launch_onesweep<K, HASV>(p, O, OV, F, FV, 6, st);
-        launch_onesweep<K, HASV>(p, F, FV, O, OV, 7, st);
+        // the passes that run read the input first and leave their result in O
+        ph.pass_out = O;
+        ph.pass_outv = OV;
+        ph.pass_tmp = F;
+        ph.pass_tmpv = FV;
+        for (u32 j = 5; j < 8; ++j) launch_onesweep<K, HASV>(ph, kin, vin, O, OV, j, st);
         launch_group_fix<HASV>(p, (const u64*)O, OV, (u64*)F, FV, st);
         launch_group_fix_mid<HASV>(p, (const u64*)O, OV, (u64*)F, FV, st);
         launch_group_mid<HASV>(p, (const u64*)O, OV, (u64*)F, FV, device_cus() * 8, st);
@@ -368,16 +376,17 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         Plan qx = q;
         qx.kx_top = top;
         qx.kx_fm = fm;
+        // only the digits that reorder some flagged block are passed over; the
+        // first pass that runs reads the input (and maps typed keys), the
+        // last writes F (the kernels pick their buffers from the digit mask)
+        qx.run_slot = C_RUN_REDO;
+        qx.run_mask = 0xFFu;
+        qx.pass_out = F;
+        qx.pass_outv = FV;
+        qx.pass_tmp = O;
+        qx.pass_tmpv = OV;
         launch_fill32(p.hist, (u64)p.NB * sh.D * RADIX, 0, st);
         launch_hist<K>(qx, kin, st);
-        launch_redo_digits(q, st);
-        // only the digits that reorder some flagged block are passed over;
-        // the first pass that runs reads the input (and maps typed keys), the
-        // last writes F (the kernels pick their buffers from the digit mask)
-        qx.redo_out = F;
-        qx.redo_outv = FV;
-        qx.redo_tmp = O;
-        qx.redo_tmpv = OV;
         for (u32 j = 0; j < sh.D; ++j) launch_onesweep<K, HASV>(qx, kin, vin, F, FV, j, st);
       } else {
         for (u32 j = 0; j < sh.D; ++j)

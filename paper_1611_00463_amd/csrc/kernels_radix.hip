@@ -307,6 +307,12 @@ __global__ __launch_bounds__(256) void k_scan_hist(Plan p) {
   u32* h = p.hist + (u64)gw * RADIX;
   const u32 a0 = h[lane * 4 + 0], a1 = h[lane * 4 + 1], a2 = h[lane * 4 + 2], a3 = h[lane * 4 + 3];
   const u32 s = a0 + a1 + a2 + a3;
+  if (p.run_slot) {
+    // two or more non-empty buckets: the pass over this digit reorders the block
+    const u32 nzl = (a0 != 0) + (a1 != 0) + (a2 != 0) + (a3 != 0);
+    const bool varies = __popcll(__ballot(nzl != 0)) >= 2 || __ballot(nzl >= 2) != 0;
+    if (varies && lane == 0) atomicOr(&p.counters[p.run_slot], 1u << (gw % p.D));
+  }
   u32 x = s;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -362,40 +368,11 @@ __device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n,
 // A tile waits only for tiles of its own queue with smaller tickets, which
 // running workgroups hold, so the waits always end.
 // REDO: a pass of the fallback plan (blocks the group fix-up flagged); it is
-// a separate instantiation so that profiles tell the two apart.  It leaves
-// at once when the plan holds no block or when the digit is the same for all
-// keys of each planned block (k_redo_digits); the passes that do run choose
-// their buffers so that the first reads the input (src0) and the last writes
-// the plan's output buffer.
-// The digit passes of the fallback plan that change any planned block's
-// order: bit j of C_REDO_DIGITS is set when some planned block has keys in
-// two or more buckets of digit j (a pass over a digit that is the same for
-// all keys of every block leaves every block as it is).  The histogram holds
-// block-relative exclusive bucket starts by now, so one bucket holds every
-// key exactly when every start is 0 or the block size.
-__global__ __launch_bounds__(1024) void k_redo_digits(Plan p) {
-  __shared__ u32 s_bits;
-  if (threadIdx.x == 0) s_bits = 0;
-  __syncthreads();
-  const u32 nl = p.counters[C_NLARGE];
-  for (u32 i = threadIdx.x; i < nl * p.D; i += 1024) {
-    const u32 blk = p.large_list[i / p.D], j = i % p.D;
-    const u32 nb = (u32)(p.blk_start[blk + 1] - p.blk_start[blk]);
-    const u32* const h = p.hist + ((u64)blk * p.D + j) * RADIX;
-    bool varies = false;
-    for (u32 d = 0; d < RADIX && !varies; ++d) varies = h[d] != 0 && h[d] != nb;
-    if (varies) atomicOr(&s_bits, 1u << j);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) p.counters[C_REDO_DIGITS] = s_bits;
-}
-
-void launch_redo_digits(const Plan& p, hipStream_t s) {
-  const int pe_ = prof_begin(s);
-  hipLaunchKernelGGL(k_redo_digits, dim3(1), dim3(1024), 0, s, p);
-  prof_end(pe_, "redo_digits", s);
-}
-
+// a separate instantiation so that profiles tell the two apart, and it
+// leaves at once when the plan holds no block.  With p.run_slot set, a pass
+// over a digit that is the same for all keys of every block does not run,
+// and the passes that do run choose their buffers: the first reads the
+// input (src0), the last writes p.pass_out.
 template <typename K, bool HASV, int NT, int ITEMS, int MINW, bool REDO>
 __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restrict__ src0,
                                                  const u32* __restrict__ srcv0, K* __restrict__ dst0,
@@ -441,18 +418,19 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
   K* dst = dst0;
   u32* dstv = dstv0;
   u64 kx_top = p.kx_top, kx_fm = p.kx_fm;  // applied to keys read from the input only
-  if (REDO) {
-    if (p.counters[C_NLARGE] == 0) return;
-    const u32 run = p.counters[C_REDO_DIGITS];  // bit j: pass j reorders some planned block
+  if (REDO && p.counters[C_NLARGE] == 0) return;
+  if (p.run_slot) {
+    u32 run = p.counters[p.run_slot] & p.run_mask;
+    if (run == 0) run = 1u << (31 - __clz(p.run_mask));  // at least one pass writes pass_out
     if (((run >> pass) & 1u) == 0) return;
     const u32 a = (u32)__popc(run & ((1u << pass) - 1u)), e = (u32)__popc(run);
-    // executed pass k writes the output buffer when e - 1 - k is even
+    // the k-th pass that runs writes pass_out when e - 1 - k is even
     const bool to_out = ((e - 1u - a) & 1u) == 0;
-    dst = (K*)(to_out ? p.redo_out : p.redo_tmp);
-    dstv = (u32*)(to_out ? p.redo_outv : p.redo_tmpv);
+    dst = (K*)(to_out ? p.pass_out : p.pass_tmp);
+    dstv = to_out ? p.pass_outv : p.pass_tmpv;
     if (a > 0) {
-      src = (const K*)(to_out ? p.redo_tmp : p.redo_out);
-      srcv = (const u32*)(to_out ? p.redo_tmpv : p.redo_outv);
+      src = (const K*)(to_out ? p.pass_tmp : p.pass_out);
+      srcv = to_out ? p.pass_tmpv : p.pass_outv;
       kx_top = kx_fm = 0;
     }
   }

@@ -46,7 +46,8 @@ enum Counter : int {
   C_NLARGE = 2,     // blocks larger than one tile
   C_NMID = 3,       // groups listed for the mid-size group sort
   C_ANYFLAG = 4,    // some block was flagged by the group fix-up
-  C_REDO_DIGITS = 5,  // bit j: fallback pass j reorders some planned block
+  C_RUN_TOP = 5,    // bit j: digit j takes two or more values in some large block (top-digit passes)
+  C_RUN_REDO = 6,   // the same over the blocks of the fallback plan
   C_QPARAM = 8,     // C_QPARAM + 4x + {0: blocks, 1: rmin, 2: first status slot, 3: tiles} of queue x
   C_TICKET = 64,    // C_TICKET + NQ * pass + x: next ticket of queue x in radix pass `pass`
   C_COUNT = 128
@@ -124,12 +125,17 @@ struct Plan {
   u64 kx_top, kx_fm;     // map applied to keys read from keys_in
   u64 ky_top, ky_fm;     // inverse applied to keys written to keys_out / splitters
   u32 vidx;              // values are generated: input position inside the instance
-  // Buffers of the fallback plan's passes (the passes that run alternate
-  // between them so that the last one writes redo_out).
-  void* redo_out;
-  u32* redo_outv;
-  void* redo_tmp;
-  u32* redo_tmpv;
+  // Digit passes that may be left out (run_slot != 0): k_scan_hist sets bit j
+  // of counters[run_slot] when digit j takes two or more values in some
+  // block; a pass of run_mask whose bit is clear leaves every block as it is
+  // and does not run (the highest pass of run_mask runs when no bit is set).
+  // The passes that run read the input first and then alternate between
+  // pass_out and pass_tmp so that the last one writes pass_out.
+  u32 run_slot, run_mask;
+  void* pass_out;
+  u32* pass_outv;
+  void* pass_tmp;
+  u32* pass_tmpv;
 };
 
 // ----------------------------------------------------------------- helpers
