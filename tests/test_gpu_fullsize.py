@@ -98,3 +98,39 @@ def test_f64_index_values_full_size():
     assert_same("cuts", u64(r.cuts)[0], plan["cuts"].astype(np.uint64))
     assert_same("send_counts", u64(r.send_counts)[0], plan["send_counts"].astype(np.uint64))
     assert_same("part_offsets", u64(r.part_offsets)[0], plan["part_offsets"].astype(np.uint64))
+
+
+def test_search_and_provenance_full_size():
+    """Search and provenance at the benchmark's size, by properties that fix
+    them: each position p satisfies sorted[p-1] < q <= sorted[p] (lower
+    bound; <= and < for the upper bound), each partition index k satisfies
+    G_k <= p < G_{k+1}; each source index splits into a block whose range
+    holds it and the offset inside that range."""
+    keys = datagen.uniform_keys_torch(N, 2, "cuda")
+    r = L.sort_pairs(keys, None, P, s=S)
+    L.check(r.workspace)
+    sk = signed(r.keys)
+    G = r.part_offsets[0].contiguous()
+    nq = 1 << 22
+    pick = datagen.u64_torch(40, 0, nq // 2, "cuda").view(torch.int64).remainder(N)
+    q = torch.cat([r.keys.view(torch.int64)[pick], datagen.u64_torch(41, 0, nq - nq // 2, "cuda").view(torch.int64)])
+    qs = q ^ SIGN
+    for upper in (False, True):
+        pos, part = L.search(r.keys, q.view(torch.uint64), upper, G)
+        below = sk[(pos - 1).clamp(min=0)]
+        at = sk[pos.clamp(max=N - 1)]
+        ok_lo = (pos == 0) | ((below <= qs) if upper else (below < qs))
+        ok_hi = (pos == N) | ((at > qs) if upper else (at >= qs))
+        assert bool((ok_lo & ok_hi).all()), "search positions inconsistent with the sorted keys"
+        k = part.view(torch.int32).to(torch.int64)
+        inside = pos < N
+        kk = k[inside]
+        assert bool(((G[kk] <= pos[inside]) & (pos[inside] < G[kk + 1])).all()), "partition of a position"
+        assert bool((k[~inside] == P).all()), "past-the-end positions belong to no partition"
+    blk, off = L.provenance(r.vals, N, P)
+    g = r.vals.view(torch.int32).to(torch.int64)
+    b = blk.view(torch.int32).to(torch.int64)
+    start = (b * N) // P
+    end = ((b + 1) * N) // P
+    assert bool(((start <= g) & (g < end)).all()), "source block does not hold the index"
+    assert bool((off.view(torch.int32).to(torch.int64) == g - start).all()), "offset inside the block"
