@@ -462,8 +462,8 @@ def main():
                     help="only run a plain device copy of BYTES three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU exchange is not "
-              f"part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
+              f"exchange (the distributed form is a design note only)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
