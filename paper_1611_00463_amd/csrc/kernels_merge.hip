@@ -187,7 +187,7 @@ __device__ inline u32 pad8(u32 q) { return q + (q >> 3); }
 // lists of `w` segments are merged pairwise (A = [a0, a1), B = [a1, b1), ties to
 // A).  The outputs are produced into registers; a thread whose range runs past
 // the end of its pair starts over in the next pair (merge-path search again).
-template <typename K, bool IDX, int IT, int F>
+template <typename K, bool IDX, int IT, int F, bool FULL>
 __device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* so, int w, u32 q0, u32 n,
                                     K (&ok)[IT], uint16_t (&oi)[IT]) {
   u32 a1 = 0, b1 = 0, ia = 0, ib = 0;
@@ -210,11 +210,12 @@ __device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* 
     ka = ia < a1 ? ck[pad8(ia)] : (K)0;
     kb = ib < b1 ? ck[pad8(ib)] : (K)0;
   };
-  if (q0 < n) start(q0);
+  // FULL: the tile holds TM outputs, so every thread's IT outputs exist
+  if (FULL || q0 < n) start(q0);
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const u32 q = q0 + i;
-    if (q < n) {
+    if (FULL || q < n) {
       if (q == b1) start(q);
       // branch-free step: emit the smaller front, reload only the side consumed
       const bool takeA = ib >= b1 || (ia < a1 && ka <= kb);
@@ -284,7 +285,10 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
   for (int w = 1; w < F; w <<= 1) {
     K ok[IT];
     uint16_t oi[IT];
-    merge_thread<K, HASV, IT, F>(s_k, s_i, s_so, w, q0, n, ok, oi);
+    if (n == (u32)TM)
+      merge_thread<K, HASV, IT, F, true>(s_k, s_i, s_so, w, q0, n, ok, oi);
+    else
+      merge_thread<K, HASV, IT, F, false>(s_k, s_i, s_so, w, q0, n, ok, oi);
     __syncthreads();
     // q0 is a multiple of IT (4, 8 or 16) and (q0 mod 8) + i < 8 whenever
     // i < 8, so pad8(q0 + i) = pad8(q0) + i + i / 8
