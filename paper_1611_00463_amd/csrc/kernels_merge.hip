@@ -268,14 +268,35 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
   __syncthreads();
   const u32 n = s_so[F];
   {
+    // source positions first, then every load at once (past n: element 0,
+    // always present when a tile exists), then the LDS stores
+    u64 e[IT];
     u32 r = 0;
-    for (u32 q = tid; q < n; q += NT) {
-      while (r + 1 < (u32)F && q >= s_so[r + 1]) ++r;
-      const u64 e = s_roff[r] + (q - s_so[r]);
-      s_k[pad8(q)] = src[e];
-      if (HASV) {
-        s_i[pad8(q)] = (uint16_t)q;
-        s_v[q] = srcv[e];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const u32 q = tid + (u32)i * NT;
+      e[i] = 0;
+      if (q < n) {
+        while (r + 1 < (u32)F && q >= s_so[r + 1]) ++r;
+        e[i] = s_roff[r] + (q - s_so[r]);
+      }
+    }
+    K kv[IT];
+    u32 vv[HASV ? IT : 1];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      kv[i] = src[e[i]];
+      if (HASV) vv[i] = srcv[e[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const u32 q = tid + (u32)i * NT;
+      if (q < n) {
+        s_k[pad8(q)] = kv[i];
+        if (HASV) {
+          s_i[pad8(q)] = (uint16_t)q;
+          s_v[q] = vv[i];
+        }
       }
     }
   }
