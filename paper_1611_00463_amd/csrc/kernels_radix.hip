@@ -228,11 +228,22 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
     const u64 tbase = p.blk_start[blk] + (u64)(t - p.tstart[blk]) * SORT_TILE;
     const u64 rem = p.blk_start[blk + 1] - tbase;
     const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
-#pragma unroll 4
-    for (int j = 0; j < SORT_TILE / SORT_NT; ++j) {
-      const u32 idx = j * SORT_NT + tid;
+    // the tile's keys are read HB at a time, all loads in flight together
+    // (a load and its use in one step made every key wait on memory alone)
+    constexpr int HB = 8;
+    static_assert((SORT_TILE / SORT_NT) % HB == 0, "whole load batches");
+    for (int j0 = 0; j0 < SORT_TILE / SORT_NT; j0 += HB) {
+    K kb[HB];
+#pragma unroll
+    for (int u = 0; u < HB; ++u) {
+      const u32 idx = (j0 + u) * SORT_NT + tid;
+      kb[u] = src[tbase + (idx < tile_n ? idx : 0)];  // clamped: tile_n >= 1
+    }
+#pragma unroll
+    for (int u = 0; u < HB; ++u) {
+      const u32 idx = (j0 + u) * SORT_NT + tid;
       const bool valid = idx < tile_n;
-      const K key = valid ? key_in<K>(src[tbase + idx], p.kx_top, p.kx_fm) : (K)0;
+      const K key = valid ? key_in<K>(kb[u], p.kx_top, p.kx_fm) : (K)0;
       bool done = !valid;
       if (have_hot) {
         // the wave's hot key (a value seen in many lanes before) first
@@ -289,6 +300,7 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
           }
         }
       }
+    }
     }
   }
   __syncthreads();
