@@ -643,37 +643,45 @@ constexpr u32 GF_SHIFT = 40;
 constexpr int GF_NT = 1024;
 constexpr u32 GF_WIN = SORT_TILE + 2 * GF_HALO;
 
+// The first fix-up works on parts of GF1_SPAN keys of a radix tile, so that
+// its LDS window is small enough for several workgroups per compute unit.
+constexpr u32 GF1_SPLIT = 2;
+constexpr u32 GF1_SPAN = SORT_TILE / GF1_SPLIT;
+constexpr int GF1_NT = 512;
+constexpr u32 GF1_WIN = GF1_SPAN + 2 * GF_HALO;
+
 template <bool HASV>
-__global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restrict__ src,
+__global__ __launch_bounds__(GF1_NT) void k_group_fix(Plan p, const u64* __restrict__ src,
                                                     const u32* __restrict__ srcv, u64* __restrict__ dst,
                                                     u32* __restrict__ dstv) {
-  constexpr u32 NW = GF_WIN / 64 + 2;  // head-bit words, with room for the block's end
-  __shared__ u64 s_k[GF_WIN];
+  constexpr u32 NW = GF1_WIN / 64 + 2;  // head-bit words, with room for the block's end
+  __shared__ u64 s_k[GF1_WIN];
   __shared__ u64 s_hb[NW];  // bit w: window position w starts a group
   __shared__ u32 s_blk;
   const u32 tid = threadIdx.x, lane = tid & 63;
-  const u32 t = blockIdx.x;
+  const u32 t = blockIdx.x / GF1_SPLIT, part = blockIdx.x % GF1_SPLIT;  // radix tile and its part
   if (t >= p.tstart[p.NB]) return;
   if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t);
-  for (u32 i = tid; i < NW; i += GF_NT) s_hb[i] = 0;
+  for (u32 i = tid; i < NW; i += GF1_NT) s_hb[i] = 0;
   __syncthreads();
   const u32 blk = s_blk;
   const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
-  const u64 ts = bs + (u64)(t - p.tstart[blk]) * SORT_TILE;
-  const u64 te = be - ts < (u64)SORT_TILE ? be : ts + SORT_TILE;
+  const u64 ts = bs + (u64)(t - p.tstart[blk]) * SORT_TILE + (u64)part * GF1_SPAN;
+  if (ts >= be) return;  // the last tile of a block may not reach this part
+  const u64 te = be - ts < (u64)GF1_SPAN ? be : ts + GF1_SPAN;
   const u64 ws = ts - bs > GF_HALO ? ts - GF_HALO : bs;
   const u64 we = be - te > GF_HALO ? te + GF_HALO : be;
   const u32 wn = (u32)(we - ws);
   const bool wfirst = ws == bs, wlast = we == be;
   // all loads issued at once: the window's keys (into LDS) and this thread's
   // values of the tile (kept in registers until the write)
-  constexpr int KL = (GF_WIN + GF_NT - 1) / GF_NT, VL = SORT_TILE / GF_NT;
+  constexpr int KL = (GF1_WIN + GF1_NT - 1) / GF1_NT, VL = GF1_SPAN / GF1_NT;
   const u32 o0 = (u32)(ts - ws), o1 = (u32)(te - ws);
   u32 v[HASV ? VL : 1];
   if (HASV) {
 #pragma unroll
     for (int k = 0; k < VL; ++k) {
-      const u32 w = o0 + (u32)k * GF_NT + tid;
+      const u32 w = o0 + (u32)k * GF1_NT + tid;
       v[k] = w < o1 ? srcv[ws + w] : 0u;
     }
   }
@@ -681,12 +689,12 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restri
     u64 kk[KL];
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
-      const u32 i = (u32)k * GF_NT + tid;
+      const u32 i = (u32)k * GF1_NT + tid;
       kk[k] = i < wn ? src[ws + i] : 0;
     }
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
-      const u32 i = (u32)k * GF_NT + tid;
+      const u32 i = (u32)k * GF1_NT + tid;
       if (i < wn) s_k[i] = kk[k];
     }
   }
@@ -695,7 +703,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restri
   // bits differ from those at w - 1; the window's first position inside a
   // block is no start (a group reaching past it counts as large), and the
   // block's end counts as one.  One ballot per 64 positions.
-  for (u32 base = 0; base < wn + 1; base += GF_NT) {
+  for (u32 base = 0; base < wn + 1; base += GF1_NT) {
     const u32 w = base + tid;
     bool h = false;
     if (w < wn) h = w == 0 ? wfirst : (s_k[w] >> GF_SHIFT) != (s_k[w - 1] >> GF_SHIFT);
@@ -707,7 +715,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix(Plan p, const u64* __restri
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < VL; ++k) {
-    const u32 w = o0 + (u32)k * GF_NT + tid;
+    const u32 w = o0 + (u32)k * GF1_NT + tid;
     if (w >= o1) break;
     const u64 key = s_k[w];
     // group bounds within 64 positions: the last start at or before w and the
@@ -746,7 +754,7 @@ template <bool HASV>
 void launch_group_fix(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s) {
   if (p.max_tiles == 0) return;
   const int pe_ = prof_begin(s);
-  hipLaunchKernelGGL(k_group_fix<HASV>, dim3(p.max_tiles), dim3(GF_NT), 0, s, p, src, srcv, dst, dstv);
+  hipLaunchKernelGGL(k_group_fix<HASV>, dim3(p.max_tiles * GF1_SPLIT), dim3(GF1_NT), 0, s, p, src, srcv, dst, dstv);
   prof_end(pe_, "group_fix", s);
 }
 template void launch_group_fix<false>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
