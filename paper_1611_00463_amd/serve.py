@@ -105,12 +105,16 @@ class Server:
                 b = inflight[si]
                 if b.done.query():
                     t = time.perf_counter() - t0
-                    for k, r in enumerate(b.reqs):
-                        r.t_done = t
-                        if self.keep_outputs:
-                            a, e = int(b.offs[k]), int(b.offs[k + 1])
-                            r.keys_out = b.keep[2].keys[a:e].clone()
-                            r.part_offsets = b.keep[2].part_offsets[k].clone()
+                    # copies on the batch's own stream: its buffers go back to
+                    # that stream's pool below and may be reused by its next
+                    # batch, which is ordered after these copies
+                    with torch.cuda.stream(b.stream):
+                        for k, r in enumerate(b.reqs):
+                            r.t_done = t
+                            if self.keep_outputs:
+                                a, e = int(b.offs[k]), int(b.offs[k + 1])
+                                r.keys_out = b.keep[2].keys[a:e].clone()
+                                r.part_offsets = b.keep[2].part_offsets[k].clone()
                     used -= b.bytes
                     n_done += len(b.reqs)
                     del inflight[si]
