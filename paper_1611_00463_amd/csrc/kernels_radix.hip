@@ -775,50 +775,52 @@ template void launch_group_fix<true>(const Plan&, const u64*, const u32*, u64*, 
 //    equal (heavy duplicates); a key of it that differs from its predecessor
 //    flags the block again (gflags2), which is then sorted over all eight
 //    digits.
-constexpr u32 GF_XWIN = SORT_TILE + 2 * GF_MID;
+constexpr u32 GF_XWIN = GF1_SPAN + 2 * GF_MID;
+constexpr u32 GF_MIDPART = GF1_SPAN / (GF_HALO + 1) + 1;  // listed groups starting in one part, at most
 
 template <bool HASV>
-__global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __restrict__ src,
+__global__ __launch_bounds__(GF1_NT) void k_group_fix_mid(Plan p, const u64* __restrict__ src,
                                                     const u32* __restrict__ srcv, u64* __restrict__ dst,
                                                     u32* __restrict__ dstv) {
   constexpr u32 NW = GF_XWIN / 64 + 2;      // head-bit words, with room for the block's end
   constexpr u32 XH = GF_MID - GF_HALO;      // outer halo: top bits only
-  __shared__ u64 s_k[GF_WIN + 1];           // keys of the tile and the inner halo (+ one spill slot)
+  __shared__ u64 s_k[GF1_WIN + 1];           // keys of the tile and the inner halo (+ one spill slot)
   __shared__ u32 s_xt[2][XH];               // top bits of the outer halo, left and right
   __shared__ u64 s_hb[NW];                  // bit x: window position x starts a group
   __shared__ u32 s_last[NW];                // last group start in words <= w (or none)
   __shared__ u32 s_first[NW];               // first group start in words >= w (or none)
-  __shared__ u64 s_mid[GF_MIDPT];  // mid-size groups starting in the tile
+  __shared__ u64 s_mid[GF_MIDPART];  // mid-size groups starting in the tile
   __shared__ u32 s_nmid, s_mbase, s_empty;
   __shared__ u32 s_blk;
   const u32 tid = threadIdx.x, lane = tid & 63;
-  const u32 t = blockIdx.x;
+  const u32 t = blockIdx.x / GF1_SPLIT, part = blockIdx.x % GF1_SPLIT;  // radix tile and its part
   if (p.counters[C_ANYFLAG] == 0 || t >= p.tstart[p.NB]) return;  // no block flagged
   if (tid == 0) {
     s_blk = find_seg(p.tstart, p.NB, t);
     s_nmid = 0;
     s_empty = 0;
   }
-  for (u32 i = tid; i < NW; i += GF_NT) s_hb[i] = 0;
+  for (u32 i = tid; i < NW; i += GF1_NT) s_hb[i] = 0;
   __syncthreads();
   const u32 blk = s_blk;
   if (p.gflags[blk] == 0) return;  // the first fix-up finished this block
   const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
-  const u64 ts = bs + (u64)(t - p.tstart[blk]) * SORT_TILE;
-  const u64 te = be - ts < (u64)SORT_TILE ? be : ts + SORT_TILE;
+  const u64 ts = bs + (u64)(t - p.tstart[blk]) * SORT_TILE + (u64)part * GF1_SPAN;
+  if (ts >= be) return;  // the last tile of a block may not reach this part
+  const u64 te = be - ts < (u64)GF1_SPAN ? be : ts + GF1_SPAN;
   // inner window [ws, we) in LDS
   const u64 ws = ts - bs > GF_HALO ? ts - GF_HALO : bs;
   const u64 we = be - te > GF_HALO ? te + GF_HALO : be;
   const u32 wn = (u32)(we - ws);
   // all loads issued at once: the inner window's keys (into LDS) and this
   // thread's values of the tile (kept in registers until the write)
-  constexpr int KL = (GF_WIN + GF_NT - 1) / GF_NT, VL = SORT_TILE / GF_NT;
+  constexpr int KL = (GF1_WIN + GF1_NT - 1) / GF1_NT, VL = GF1_SPAN / GF1_NT;
   const u32 o0 = (u32)(ts - ws), o1 = (u32)(te - ws);
   u32 v[HASV ? VL : 1];
   if (HASV) {
 #pragma unroll
     for (int k = 0; k < VL; ++k) {
-      const u32 w = o0 + (u32)k * GF_NT + tid;
+      const u32 w = o0 + (u32)k * GF1_NT + tid;
       v[k] = w < o1 ? srcv[ws + w] : 0u;
     }
   }
@@ -826,7 +828,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
     u64 kk[KL];
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
-      const u32 i = (u32)k * GF_NT + tid;
+      const u32 i = (u32)k * GF1_NT + tid;
       kk[k] = src[ws + (i < wn ? i : wn - 1)];  // clamped, not predicated: all loads in flight together
     }
     // positions past wn take clamped copies, which nothing reads; those past
@@ -834,8 +836,8 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
     // is moved behind the wait of the others)
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
-      const u32 i = (u32)k * GF_NT + tid;
-      s_k[i < GF_WIN ? i : GF_WIN] = kk[k];
+      const u32 i = (u32)k * GF1_NT + tid;
+      s_k[i < GF1_WIN ? i : GF1_WIN] = kk[k];
     }
   }
   __syncthreads();
@@ -851,7 +853,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
   const u32 nl = (u32)(ws - xs), nr = (u32)(xe - we);  // outer halo lengths (<= XH)
   if (need_l || need_r) {
     // top bits of the outer halo: one position per thread and side
-    static_assert(XH <= (u32)GF_NT, "one outer-halo position per thread");
+    static_assert(XH <= (u32)GF1_NT, "one outer-halo position per thread");
     const u32* const hi = reinterpret_cast<const u32*>(src) + 1;  // high words: hi[2 g]
     if (tid < nl) s_xt[0][tid] = hi[2 * (xs + tid)] >> (GF_SHIFT - 32);
     if (tid < nr) s_xt[1][tid] = hi[2 * (we + tid)] >> (GF_SHIFT - 32);
@@ -874,7 +876,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
   // either way.)
   const bool xfirst = xs == bs, xlast = xe == be;
   if (nl == 0 && nr == 0) {
-    for (u32 base = 0; base < xn + 1; base += GF_NT) {
+    for (u32 base = 0; base < xn + 1; base += GF1_NT) {
       const u32 x = base + tid;
       bool h = false;
       if (x < xn) h = x == 0 ? xfirst : (s_k[x] >> GF_SHIFT) != (s_k[x - 1] >> GF_SHIFT);
@@ -886,7 +888,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
       }
     }
   } else {
-    for (u32 base = 0; base < xn + 1; base += GF_NT) {
+    for (u32 base = 0; base < xn + 1; base += GF1_NT) {
       const u32 x = base + tid;
       bool h = false;
       if (x < xn) h = x == 0 ? xfirst : top(x) != top(x - 1);
@@ -957,7 +959,7 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
 #pragma unroll
   for (int k = 0; k < VL; ++k) {
     place[k] = NONE;
-    const u32 w = o0 + (u32)k * GF_NT + tid;  // inner-window position
+    const u32 w = o0 + (u32)k * GF1_NT + tid;  // inner-window position
     if (w >= o1) break;
     const u32 x = w + nl;                      // outer-window position
     const u64 key = s_k[w];
@@ -1006,14 +1008,14 @@ __global__ __launch_bounds__(GF_NT) void k_group_fix_mid(Plan p, const u64* __re
     if (tid == 0) s_mbase = atomicAdd(&p.counters[C_NMID], nm);
     __syncthreads();
     const u32 base = s_mbase;
-    for (u32 i = tid; i < nm; i += GF_NT) {
+    for (u32 i = tid; i < nm; i += GF1_NT) {
       if ((u64)base + i < p.mid_cap) p.midlist[base + i] = s_mid[i];
       else bad = true;  // cannot happen for a list of n / (GF_HALO + 1) + 1 entries; the block is redone
     }
   }
 #pragma unroll
   for (int k = 0; k < VL; ++k) {
-    const u32 w = o0 + (u32)k * GF_NT + tid;
+    const u32 w = o0 + (u32)k * GF1_NT + tid;
     if (w >= o1) break;
     if (place[k] != NONE) {
       dst[xs + place[k]] = s_k[w];
@@ -1027,7 +1029,7 @@ template <bool HASV>
 void launch_group_fix_mid(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s) {
   if (p.max_tiles == 0) return;
   const int pe_ = prof_begin(s);
-  hipLaunchKernelGGL(k_group_fix_mid<HASV>, dim3(p.max_tiles), dim3(GF_NT), 0, s, p, src, srcv, dst, dstv);
+  hipLaunchKernelGGL(k_group_fix_mid<HASV>, dim3(p.max_tiles * GF1_SPLIT), dim3(GF1_NT), 0, s, p, src, srcv, dst, dstv);
   prof_end(pe_, "group_fix_mid", s);
 }
 template void launch_group_fix_mid<false>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
