@@ -299,14 +299,3 @@ def sample_sort(keys: np.ndarray, vals: np.ndarray | None, P: int, s: int = 0,
                       splitters=splitters, send_counts=C, cuts=cuts, samples=samples,
                       sorted_blocks=sk, sorted_vals=sv, lo=lo, hi=hi, recv_offsets=D)
 
-
-def sample_sort_batch(keys: np.ndarray, vals: np.ndarray | None, seg_offsets, P: int,
-                      s: int = 0, mode: int = INV_COUNT) -> list[SortResult]:
-    """Several independent data sets sorted at once (Section IV.C): here simply
-    one run of the method per segment."""
-    out = []
-    offs = [int(x) for x in seg_offsets]
-    for b in range(len(offs) - 1):
-        a, e = offs[b], offs[b + 1]
-        out.append(sample_sort(keys[a:e], None if vals is None else vals[a:e], P, s, mode))
-    return out

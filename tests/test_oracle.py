@@ -321,3 +321,144 @@ def test_table_t2_uniform_share():
     share = r.part_counts / len(keys)
     assert share.max() <= bound
     assert abs(share.sum() - 1.0) < 1e-12
+
+
+# ------------------------------------------------------------------ partition_plan
+# partition_plan (steps 1-5 without moving data) is the reference of the
+# full-size metadata checks, so it is pinned here: against the whole method
+# (sample_sort, itself pinned above by Python's sorted, brute force and the
+# worked example) field by field, and directly against brute force.
+def _plan_vs_sample_sort(keys, P, s, mode):
+    plan = O.partition_plan(keys, P, s, mode)
+    r = O.sample_sort(keys, np.arange(len(keys), dtype=np.uint32), P, s, mode)
+    assert [x.tolist() for x in plan["samples"]] == [x.tolist() for x in r.samples]
+    assert plan["splitters"].tolist() == r.splitters.tolist()
+    assert plan["lo"].tolist() == r.lo.tolist() and plan["hi"].tolist() == r.hi.tolist()
+    assert plan["cuts"].tolist() == r.cuts.tolist()
+    assert plan["send_counts"].tolist() == r.send_counts.tolist()
+    assert plan["part_offsets"].tolist() == r.part_offsets.tolist()
+    assert plan["part_counts"].tolist() == r.part_counts.tolist()
+    assert plan["recv_offsets"].tolist() == r.recv_offsets.tolist()
+    return plan
+
+
+@pytest.mark.parametrize("mode", [O.INV_COUNT, O.INV_NONE, O.INV_PAPER])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64, np.int32, np.int64])
+def test_partition_plan_matches_whole_method(mode, dtype):
+    rng = np.random.default_rng(101 + mode)
+    info = np.iinfo(dtype)
+    for trial in range(120):
+        n = int(rng.integers(0, 60))
+        P = int(rng.integers(1, 12))          # includes N < P
+        s = int(rng.integers(0, 7))           # 0: the default budget
+        if trial % 3 == 0:                    # heavy duplicates, extremes of the type
+            alpha = np.array([info.min, info.min, 0, 1, 1, 1, info.max], dtype=dtype)
+            keys = alpha[rng.integers(0, len(alpha), size=n)]
+        else:
+            keys = rng.integers(info.min, info.max, size=n, dtype=dtype, endpoint=True)
+        _plan_vs_sample_sort(keys, P, s, mode)
+
+
+def test_partition_plan_typed_total_order():
+    """Float keys reach partition_plan through their totalOrder integer image,
+    as in the full-size float check."""
+    from oracle import typed as T
+    rng = np.random.default_rng(23)
+    specials = np.array([np.nan, -np.nan, np.inf, -np.inf, 0.0, -0.0, 1.5, -1.5], dtype=np.float64)
+    for trial in range(80):
+        n = int(rng.integers(0, 50))
+        P = int(rng.integers(1, 10))
+        x = rng.normal(size=n)
+        if n:
+            x[rng.integers(0, n, size=max(1, n // 4))] = specials[rng.integers(0, len(specials), size=max(1, n // 4))]
+        ti = T.total_order_int(x)
+        for mode in (O.INV_COUNT, O.INV_NONE, O.INV_PAPER):
+            plan = _plan_vs_sample_sort(ti, P, int(rng.integers(1, 6)), mode)
+            assert plan["part_offsets"][-1] == n
+
+
+def test_partition_plan_brute_force():
+    """Directly: COUNT offsets are clamp(floor(kN/P), #<v, #<=v); COUNT cuts
+    are the block shares of the first G_k stable-order elements; NONE cuts
+    are lower bounds; PAPER cuts split each block's equal range into d+1
+    pieces; send counts and receive offsets tile the output."""
+    rng = np.random.default_rng(29)
+    for trial in range(150):
+        n = int(rng.integers(0, 45))
+        P = int(rng.integers(1, 9))
+        s = int(rng.integers(1, 6))
+        keys = rand_keys(rng, n, ALPHA if trial % 2 else [4, 4, 4, 7, 9])
+        order = brute_stable_order(keys)
+        bounds = [i * n // P for i in range(P + 1)]
+        blocks = [sorted(int(x) for x in keys[bounds[i]:bounds[i + 1]]) for i in range(P)]
+        block_of = [next(b for b in range(P) if bounds[b] <= j < bounds[b + 1]) for j in range(n)]
+        for mode in (O.INV_COUNT, O.INV_NONE, O.INV_PAPER):
+            plan = O.partition_plan(keys, P, s, mode)
+            G, c, C, D = plan["part_offsets"], plan["cuts"], plan["send_counts"], plan["recv_offsets"]
+            v = [int(x) for x in plan["splitters"]]
+            assert G[0] == 0 and G[P] == n
+            for i in range(P):
+                assert c[i, 0] == 0 and c[i, P] == len(blocks[i])
+                for k in range(1, P):
+                    less = sum(1 for x in blocks[i] if x < v[k - 1])
+                    leq = sum(1 for x in blocks[i] if x <= v[k - 1])
+                    assert plan["lo"][i, k - 1] == less and plan["hi"][i, k - 1] == leq
+                    assert less <= c[i, k] <= leq
+                    if mode == O.INV_NONE:
+                        assert c[i, k] == less
+            for k in range(1, P):
+                less, leq = brute_counts(keys, v[k - 1])
+                if mode == O.INV_COUNT:
+                    assert G[k] == min(max(k * n // P, less), leq)
+                    first = order[:G[k]]
+                    for i in range(P):
+                        assert c[i, k] == sum(1 for j in first if block_of[j] == i)
+            if mode == O.INV_PAPER:
+                k = 1
+                while k < P:
+                    d = 1
+                    while k + d < P and v[k + d - 1] == v[k - 1]:
+                        d += 1
+                    for i in range(P):
+                        lo_i = sum(1 for x in blocks[i] if x < v[k - 1])
+                        m = sum(1 for x in blocks[i] if x == v[k - 1])
+                        for t in range(d):
+                            want = lo_i + ((t + 1) * m // (d + 1) if d > 1 else 0)
+                            assert c[i, k + t] == want
+                    k += d
+            # send counts, offsets and receive offsets tile [0, n) exactly once
+            cover = [0] * n
+            for i in range(P):
+                for k in range(P):
+                    assert C[i, k] == c[i, k + 1] - c[i, k]
+                    assert G[k] <= D[i, k] and D[i, k] + C[i, k] <= G[k + 1]
+                    for j in range(int(D[i, k]), int(D[i, k] + C[i, k])):
+                        cover[j] += 1
+            assert cover == [1] * n
+            assert plan["part_counts"].tolist() == [int(G[k + 1] - G[k]) for k in range(P)]
+
+
+def test_partition_plan_worked_example():
+    common, modes = load_worked_example()
+    keys = np.array(common["keys"], dtype=np.uint64)
+    P, s = common["P"][0], common["s"][0]
+    ids = {"COUNT": O.INV_COUNT, "NONE": O.INV_NONE, "PAPER": O.INV_PAPER}
+    for name, exp in modes.items():
+        plan = O.partition_plan(keys, P, s, ids[name])
+        assert plan["splitters"].tolist() == common["splitters"]
+        assert plan["cuts"].tolist() == exp["cuts"]
+        assert plan["part_offsets"].tolist() == exp["part_offsets"]
+        if "recv_offsets" in exp:
+            assert plan["recv_offsets"].tolist() == exp["recv_offsets"]
+
+
+def test_partition_plan_default_budget():
+    """s = 0 takes the default budget; blocks larger than it are sampled
+    exactly that many times (512 for 64-bit keys at P = 64, 3270 at P = 10)."""
+    rng = np.random.default_rng(31)
+    for P, n, want in ((64, 64 * 600 + 17, 512), (10, 10 * 4000 + 3, 3270)):
+        keys = rng.integers(0, 2 ** 64, size=n, dtype=np.uint64)
+        keys[rng.integers(0, n, size=n // 3)] = 12345
+        for mode in (O.INV_COUNT, O.INV_PAPER):
+            plan = _plan_vs_sample_sort(keys, P, 0, mode)
+            assert all(len(x) == want for x in plan["samples"])
