@@ -130,6 +130,36 @@ int lbsort_sort_pairs(int key_type, int val_type, const void *keys_in, const voi
                       const lbsort_parts *parts, void *ws, size_t *ws_bytes, void *stream);
 
 /*
+ * Allocation-free form of lbsort_sort_pairs, for callers that cannot
+ * allocate device memory at all (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments and results as
+ * lbsort_sort_pairs (val_type may also be LBSORT_NOVAL: keys only), but no
+ * workspace: the scratch space is one static device array of
+ * LBSORT_NOALLOC_SCRATCH_BYTES inside the library, of which every device the
+ * library runs on holds its own copy until the process ends.  Nothing is
+ * allocated by this call (no hipMalloc, no hipFree, no allocating library
+ * routine); the first call made with a device current looks up the array's
+ * address on that device.  The call runs on the current device and `stream`
+ * must belong to it.
+ *
+ * Limit: a problem whose workspace (as lbsort_sort_pairs would size it)
+ * exceeds LBSORT_NOALLOC_SCRATCH_BYTES returns LBSORT_ERR_UNSUPPORTED before
+ * anything is enqueued; that is about 5 million 64-bit keys with values, or
+ * 8 million 32-bit keys with values.
+ *
+ * All calls on one device share that device's array and each call starts
+ * by clearing what must start at zero: calls that overlap on one device
+ * (different streams, or host threads) race and give undefined results;
+ * serialise them.  dev_err (device, may be NULL) receives the device error
+ * bits this call latched (0 = none; see lbsort_check), written on `stream`
+ * after the sort.
+ */
+#define LBSORT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int lbsort_sort_pairs_noalloc(int key_type, int val_type, const void *keys_in, const void *vals_in,
+                              void *keys_out, void *vals_out, uint64_t n, const lbsort_params *params,
+                              const lbsort_parts *parts, uint32_t *dev_err, void *stream);
+
+/*
  * Sort B independent instances at once ("sort multiple different data
  * simultaneously", Section IV.C).  Instance b is input positions
  * [seg_offsets[b], seg_offsets[b+1]) of keys_in/vals_in and is sorted into the

@@ -444,6 +444,43 @@ static int dispatch(const Shape& sh, const void* kin, const void* vin, void* kou
   return run<u32, false>(sh, lay, (const u32*)kin, nullptr, (u32*)kout, nullptr, seg, parts, w, st);
 }
 
+// ----------------------------------------------------------------- static scratch
+// Scratch of the allocation-free entry point: a file-scope device array
+// (each device the library runs on holds its own copy until the process
+// ends).  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is taken once per device with
+// hipGetSymbolAddress, and only that address is handed to kernels.
+constexpr u64 NOALLOC_SCRATCH_BYTES = LBSORT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current).
+static int scratch_ptr(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(LBSORT_ERR_UNSUPPORTED, "device %d beyond the %d supported", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LBSORT_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBSORT_OK;
+}
+
+// The call's latched device error bits, copied out for the caller.
+__global__ void k_copy_err(const u32* counters, u32* out) {
+  if (threadIdx.x == 0) *out = counters[C_ERR];
+}
+
 }  // namespace lbs
 
 using namespace lbs;
@@ -465,6 +502,32 @@ int lbsort_sort_pairs(int key_type, int val_type, const void* keys_in, const voi
   int rc = make_shape(key_type, val_type, 1, n, params, false, sh);
   if (rc) return rc;
   return dispatch(sh, keys_in, vals_in, keys_out, vals_out, nullptr, parts, ws, ws_bytes, stream);
+}
+
+int lbsort_sort_pairs_noalloc(int key_type, int val_type, const void* keys_in, const void* vals_in, void* keys_out,
+                              void* vals_out, uint64_t n, const lbsort_params* params, const lbsort_parts* parts,
+                              uint32_t* dev_err, void* stream) {
+  Shape sh;
+  int rc = make_shape(key_type, val_type, 1, n, params, false, sh);
+  if (rc) return rc;
+  const Layout lay = make_layout(sh);
+  if (lay.total > NOALLOC_SCRATCH_BYTES)
+    return fail(LBSORT_ERR_UNSUPPORTED,
+                "n = %llu needs %llu bytes of scratch; the allocation-free entry point has %llu (use lbsort_sort_pairs "
+                "with a workspace)",
+                (unsigned long long)n, (unsigned long long)lay.total, (unsigned long long)NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  rc = scratch_ptr(&ws);
+  if (rc) return rc;
+  size_t have = (size_t)NOALLOC_SCRATCH_BYTES;
+  rc = dispatch(sh, keys_in, vals_in, keys_out, vals_out, nullptr, parts, ws, &have, stream);
+  if (rc) return rc;
+  if (dev_err) {
+    hipLaunchKernelGGL(k_copy_err, dim3(1), dim3(64), 0, (hipStream_t)stream, (const u32*)ws, dev_err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  }
+  return LBSORT_OK;
 }
 
 int lbsort_sort_batch(int key_type, int val_type, const void* keys_in, const void* vals_in, void* keys_out,

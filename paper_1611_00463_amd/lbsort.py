@@ -41,7 +41,7 @@ class Parts(ctypes.Structure):
 EXPORTS = ("lbsort_sort_keys", "lbsort_sort_pairs", "lbsort_sort_batch", "lbsort_local_sort",
            "lbsort_check", "lbsort_status_string", "lbsort_last_error", "lbsort_autotune",
            "lbsort_load_tuning", "lbsort_profile_enable", "lbsort_profile_read", "lbsort_search",
-           "lbsort_provenance")
+           "lbsort_provenance", "lbsort_sort_pairs_noalloc")
 
 _lib = None
 
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
     lib.lbsort_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     lib.lbsort_search.argtypes = [i32, vp, u64, vp, u64, i32, vp, u32, vp, vp, vp]
     lib.lbsort_provenance.argtypes = [vp, u64, u64, u32, vp, vp, vp]
+    lib.lbsort_sort_pairs_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, u64, pp, pa, vp, vp]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     lib.lbsort_status_string.restype = ctypes.c_char_p
