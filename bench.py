@@ -1,6 +1,6 @@
 """Benchmark of the load-balanced sample sort on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pairs|dups|keys1m]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pairs|dups|keys1m|...]
 
 Default workload (the metric's configuration): 268,435,456 uniform u64 keys,
 each with a u32 payload equal to its input index, P = 64 virtual processors,
@@ -9,17 +9,24 @@ sort (steps 1-6 of Section IV) of device-resident input.  Prints one JSON line.
 
 Measurement:
 * value: keys sorted per second over K timed steps (GKeys/s), events on the
-  stream the sort runs on, inputs already in HBM;
-* roofline: the dominant kernel (the one with the largest share of the step)
-  with its algorithmic bytes per launch divided by its average launch time,
-  both taken live from per-launch HIP events; the whole pipeline's fraction
-  of the byte model (K+V)(2D+2)+K per key is reported beside it;
+  stream the sort runs on, inputs already in HBM, no per-launch
+  instrumentation in that loop;
+* kernels / roofline: a second loop of K steps with every launch bracketed by
+  HIP events on the sort's stream: the dominant kernel (largest share of the
+  step) with its algorithmic bytes per launch divided by its average launch
+  time;
 * roofline.traffic: HBM bytes one launch of that kernel moved (FETCH_SIZE +
   WRITE_SIZE, each scaled by what the same counter reads for a plain copy of
   known size), read from the committed rocprofv3 summary of this workload
   under profiles/; null when there is none or when the kernel's source file
   has changed since the counters were taken;
-* cpu_baseline: the CPU oracle on a bounded sample of the same workload.
+* pipeline: the algorithmic bytes of the kernels the step actually launched,
+  per key and as a fraction of peak, beside the fixed 8-pass byte model;
+* dups / batched (default run only): the duplicate-heavy configuration
+  (balance and rate) and the batched configuration (one graph launch with
+  autotuned settings against a per-instance loop), each checked on the device;
+* cpu_baseline: the CPU oracle on a bounded sample of the same workload, on
+  all host cores (steps 1 and 6 over a process pool) and on one thread.
 """
 from __future__ import annotations
 
@@ -61,14 +68,26 @@ WORKLOADS = {
 
 
 def kernel_bytes_per_launch(name, n, kb, vb):
-    """Algorithmic bytes one launch of a bulk kernel moves (per key figure x keys)."""
-    if name in ("onesweep", "merge"):
+    """Algorithmic bytes one launch of a bulk kernel moves over n keys (per key
+    figure x keys); None for kernels whose work is metadata or depends on the
+    data (the mid-size fix-up and the fallback passes, empty launches on
+    uniform keys)."""
+    if name in ("onesweep", "merge", "group_fix", "small_sort"):
         return n * 2 * (kb + vb)          # read key+value, write key+value
     if name == "hist":
         return n * kb                     # read keys once for all digit counts
-    if name == "group_fix":
-        return n * 2 * (kb + vb)          # read keys and values, write them once
     return None
+
+
+def executed_bytes(prof, steps, n_of, kb, vb):
+    """Algorithmic bytes per step of the kernels the step launched: n_of(name)
+    gives the keys one launch of that kernel covers."""
+    total = 0
+    for name, (cnt, _) in prof.items():
+        per = kernel_bytes_per_launch(name, n_of(name), kb, vb)
+        if per:
+            total += per * cnt / steps
+    return total
 
 
 def measured_traffic(kernel, workload):
@@ -118,32 +137,116 @@ def make_input(w, device):
     return keys, vals
 
 
-def cpu_baseline(w, sample_n):
-    """The CPU oracle as it stands, on the first sample_n keys of the workload."""
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
+def cpu_baseline(w, n_all, n_one):
+    """The CPU oracle as it stands, on bounded samples of the same workload
+    (the first keys, same P and s): on all host cores, with the oracle's steps
+    1 and 6 over a process pool (at most 16 workers, the host share of one
+    GPU), and on one thread."""
     import numpy as np
+    from oracle import parallel as OP
     from oracle import sample_sort as O
-    from paper_1611_00463_amd import datagen
     from oracle import typed as T
+    from paper_1611_00463_amd import datagen
+    nproc, model = cpu_info()
+    workers = max(1, min(16, nproc or 1))
     if w["gen"] == "uniform":
-        keys = datagen.uniform_keys(sample_n, seed=w["seed"])
+        keys = datagen.uniform_keys(n_all, seed=w["seed"])
     elif w["gen"] == "typed":
-        keys = datagen.typed_keys(sample_n, seed=w["seed"], dtype=getattr(np, w["dtype"]))
+        keys = datagen.typed_keys(n_all, seed=w["seed"], dtype=getattr(np, w["dtype"]))
     else:
-        keys = datagen.duplicate_heavy_keys(sample_n, seed=w["seed"])
-    vals = datagen.index_values(sample_n) if w["vals"] else None
+        keys = datagen.duplicate_heavy_keys(n_all, seed=w["seed"])
+    vals = datagen.index_values(n_all) if w["vals"] else None
+    ikeys = T.total_order_int(keys) if keys.dtype.kind == "f" else keys
     t0 = time.perf_counter()
-    T.sample_sort_typed(keys, vals, w["P"], w["s"], O.INV_COUNT)
-    dt = time.perf_counter() - t0
-    return {"value": round(sample_n / dt / 1e9, 6), "unit": "GKeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_n} keys of the same workload (same P and s), numpy oracle, one thread, "
-                      f"{dt:.2f} s"}
+    OP.sample_sort_parallel(ikeys, vals, w["P"], w["s"], O.INV_COUNT, workers=workers)
+    dt_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    T.sample_sort_typed(keys[:n_one], None if vals is None else vals[:n_one], w["P"], w["s"], O.INV_COUNT)
+    dt_one = time.perf_counter() - t0
+    return {"value": round(n_all / dt_all / 1e9, 6), "unit": "GKeys/s", "cores": workers, "kind": "oracle",
+            "nproc": nproc, "cpu_model": model,
+            "sample": f"first {n_all} keys of the same workload (same P and s), numpy oracle with steps 1 and 6 "
+                      f"over {workers} worker processes, {dt_all:.2f} s wall (worker start-up included)",
+            "one_thread": {"value": round(n_one / dt_one / 1e9, 6), "unit": "GKeys/s", "cores": 1,
+                           "sample": f"first {n_one} keys, numpy oracle, one thread, {dt_one:.2f} s"}}
 
 
-def bench_batch(args):
+def check_batch_on_device(plan, keys, seg, sizes, P):
+    """Every instance of a batched sort, on the device: keys non-decreasing,
+    (key, value) pairs a permutation of the instance (values are local input
+    positions), equal keys in position order (stable), and each partition
+    offset G_k = clamp(floor(k n / P), #keys < v_k, #keys <= v_k) for the
+    instance's splitter v_k (the count-based investigator), read from the
+    sorted keys themselves."""
+    import numpy as np
+    import torch
+    total = int(sizes.sum())
+    seg64 = seg.view(torch.int64)
+    u = lambda t: t.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    kin = u(keys)
+    seen = torch.zeros(total, dtype=torch.int32, device=keys.device)
+    CH = 1 << 27
+    for a in range(0, total, CH):
+        e = min(total, a + CH)
+        idx = torch.arange(a, e, device=keys.device, dtype=torch.int64)
+        seg_of = torch.searchsorted(seg64, idx, right=True) - 1
+        ko, vo = u(plan.keys_out[a:e]), plan.vals_out[a:e].view(torch.int32).to(torch.int64)
+        n_of = seg64[seg_of + 1] - seg64[seg_of]
+        assert bool(((vo >= 0) & (vo < n_of)).all()), "batched output: value outside its instance"
+        src = seg64[seg_of] + vo
+        assert bool((kin[src] == ko).all()), "batched output: pairs broken"
+        seen.index_add_(0, src, torch.ones_like(src, dtype=torch.int32))
+        same = seg_of[1:] == seg_of[:-1]
+        assert bool((ko[1:][same] >= ko[:-1][same]).all()), "batched output not sorted within instances"
+        eq = same & (ko[1:] == ko[:-1])
+        assert bool((vo[1:][eq] > vo[:-1][eq]).all()), "batched output not stable"
+        del idx, seg_of, ko, vo, n_of, src, same, eq
+    assert bool((seen == 1).all()), "batched output is not a permutation of its instances"
+    del seen, kin
+    ko = u(plan.keys_out)
+    edges = torch.arange(CH, total, CH, device=keys.device)
+    if edges.numel():
+        inside = (torch.searchsorted(seg64, edges, right=True) == torch.searchsorted(seg64, edges - 1, right=True))
+        assert bool((ko[edges][inside] >= ko[edges - 1][inside]).all()), "batched output not sorted"
+    # partition offsets against the splitters, instance by instance
+    B = seg.numel() - 1
+    G = plan.part_offsets                                   # [B, P+1]
+    n = torch.from_numpy(sizes.astype(np.int64)).to(keys.device)
+    assert bool((G[:, 0] == 0).all() and (G[:, P] == n).all() and (G[:, 1:] >= G[:, :-1]).all()), "offsets"
+    if P > 1:
+        v = u(plan.splitters)                               # [B, P-1]
+        k = torch.arange(1, P, device=keys.device, dtype=torch.int64)
+        T_ = (k[None, :] * n[:, None]) // P
+        Gk = G[:, 1:P]
+        base = seg64[:B, None]
+        below = torch.where(Gk > 0, ko[(base + Gk - 1).clamp(min=0, max=total - 1)], torch.full_like(Gk, -1))
+        at = torch.where(Gk < n[:, None], ko[(base + Gk).clamp(max=total - 1)], torch.full_like(Gk, 1 << 40))
+        # any G in [#<v, #<=v] has below <= v <= at; G above T must be #<v
+        # (below < v), G below T must be #<=v (at > v)
+        ok = (below <= v) & (at >= v)
+        ok &= torch.where(Gk == T_, torch.ones_like(ok), torch.where(Gk > T_, below < v, at > v))
+        assert bool(ok.all()), "partition offsets differ from the count-based investigator"
+
+
+def run_batch(args, steps, warmup, tune=True, check=True):
     """Batched form: B uneven u32 key/value instances (sizes log-uniform in
     [1K, 4M], uniform / normal / sorted / reverse keys), P = 8, sorted by one
-    lbsort_sort_batch call replayed from a HIP graph, against a loop of B
-    lbsort_sort_pairs calls over the same instances on the same stream."""
+    lbsort_sort_batch call replayed from a HIP graph with autotuned settings,
+    against a loop of B lbsort_sort_pairs calls over the same instances on
+    the same stream."""
     import numpy as np
     import torch
     from paper_1611_00463_amd import datagen
@@ -153,48 +256,49 @@ def bench_batch(args):
     print(f"[bench] generating a batch of {B} instances", file=sys.stderr, flush=True)
     keys, vals, seg, sizes = datagen.batch_u32_torch(B, 4, device="cuda")
     total = int(sizes.sum())
+    tuned = None
+    if tune:
+        print("[bench] autotuning the batch", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        tuned = L.autotune(L.U32, L.VAL_U32, P, keys=keys, vals=vals, seg_offsets=seg)
+        tuned["tuning_s"] = round(time.perf_counter() - t0, 2)
+    used = L.resolve_params(L.U32, L.VAL_U32, P, total, B=B)
     plan = L.BatchPlan(keys, seg, P, vals=vals)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.run()
     torch.cuda.synchronize()
     plan.check()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.run()
     e1.record()
     torch.cuda.synchronize()
-    ms_eager = e0.elapsed_time(e1) / args.steps
+    ms_eager = e0.elapsed_time(e1) / steps
+    # kernel split from one instrumented eager run
+    lib.lbsort_profile_enable(1)
+    profile_read(lib)
+    plan.run()
+    torch.cuda.synchronize()
+    lib.lbsort_profile_enable(0)
+    prof = profile_read(lib)
     plan.capture()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.replay()
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.replay()
     e1.record()
     torch.cuda.synchronize()
-    ms_graph = e0.elapsed_time(e1) / args.steps
+    ms_graph = e0.elapsed_time(e1) / steps
     plan.check()
-    # check, in chunks: every instance sorted and a permutation of its input
-    seg64 = seg.view(torch.int64)
-    CH = 1 << 27
-    for a in range(0, total, CH):
-        e = min(total, a + CH)
-        idx = torch.arange(a, e, device="cuda", dtype=torch.int64)
-        seg_of = torch.searchsorted(seg64, idx, right=True) - 1
-        ko = plan.keys_out[a:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
-        vo = plan.vals_out[a:e].view(torch.int32).to(torch.int64)
-        src = seg64[seg_of] + vo
-        ki = keys.view(torch.int32)[src].to(torch.int64) & 0xFFFFFFFF
-        assert bool((ki == ko).all()), "batched output is not a permutation of its instances"
-        same = seg_of[1:] == seg_of[:-1]
-        assert bool((ko[1:][same] >= ko[:-1][same]).all()), "batched output not sorted within instances"
-        del idx, seg_of, ko, vo, src, ki, same
+    if check:
+        check_batch_on_device(plan, keys, seg, sizes, P)
     # the per-instance loop
     kout = torch.empty_like(keys)
     vout = torch.empty_like(vals)
-    prm = L.Params(P, 0, 0, 0, 0, 0)
+    prm = L.Params(P, 0, 0, used["fanin"], used["merge_tile"], used["radix_tile"], 0)
     offs = torch.empty((B, P + 1), dtype=torch.int64, device="cuda")
     need = ctypes.c_size_t(0)
     parts = L.Parts(offs.data_ptr(), 0, 0, 0, 0)
@@ -219,7 +323,7 @@ def bench_batch(args):
 
     loop()
     torch.cuda.synchronize()
-    loops = max(1, args.steps // 5)
+    loops = max(1, steps // 5)
     t0 = time.perf_counter()
     e0.record()
     for _ in range(loops):
@@ -231,17 +335,46 @@ def bench_batch(args):
     i32 = lambda t: t.view(torch.int32)
     assert torch.equal(i32(kout), i32(plan.keys_out)) and torch.equal(i32(vout), i32(plan.vals_out)), \
         "loop and batch differ"
+    assert torch.equal(offs, plan.part_offsets), "loop and batch partition offsets differ"
+    # roofline of the dominant kernel: onesweep covers the keys of blocks
+    # larger than one LDS sort (4096 keys), small_sort the others
+    bsz = np.diff((np.arange(P + 1)[None, :] * sizes.astype(np.int64)[:, None]) // P, axis=1)
+    n_large = int(bsz[bsz > 4096].sum())
+    n_of = lambda name: n_large if name in ("onesweep", "hist") else (total - n_large if name == "small_sort" else total)
+    dom = max(((k, t) for k, (c, t) in prof.items() if kernel_bytes_per_launch(k, n_of(k), 4, 4)),
+              key=lambda x: x[1])[0]
+    c, t = prof[dom]
+    per_launch = kernel_bytes_per_launch(dom, n_of(dom), 4, 4)
+    achieved = per_launch / (t / c / 1e3) / 1e9
+    ex = executed_bytes(prof, 1, n_of, 4, 4)
+    value = total / (ms_graph / 1e3) / 1e9
+    return {
+        "value": round(value, 4), "unit": "GKeys/s", "ms_per_step": round(ms_graph, 4),
+        "config": {"workload": f"batching: {B} uint32 key-value instances, sizes log-uniform in [1K, 4M], "
+                               f"uniform/normal/sorted/reverse keys, P=8, one HIP-graph launch, autotuned",
+                   "instances": B, "total_keys": total, "P": P, "keys_in_blocks_above_4096": n_large},
+        "settings": used, "autotuned": tuned,
+        "eager_ms": round(ms_eager, 4), "graph_ms": round(ms_graph, 4),
+        "loop_ms": round(ms_loop, 4), "loop_wall_ms": round(wall_loop, 2),
+        "loop_GKeys_s": round(total / (ms_loop / 1e3) / 1e9, 4),
+        "speedup_vs_loop": round(ms_loop / ms_graph, 3),
+        "checked": "on the device: sorted, permutation, stable, offsets = count-based clamp" if check else None,
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": per_launch, "avg_launch_ms": round(t / c, 5)},
+        "pipeline": {"executed_bytes_per_key": round(ex / total, 2),
+                     "executed_frac": round(value * ex / total / HBM_PEAK_GBS, 4)},
+        "kernels": {k: {"launches": c, "ms": round(t, 5)} for k, (c, t) in prof.items()},
+    }
+
+
+def bench_batch(args):
+    b = run_batch(args, args.steps, args.warmup)
     line = {"metric": "batched sort: GKeys/s (u32 keys + u32 values), one graph launch vs a per-instance loop",
-            "value": round(total / (ms_graph / 1e3) / 1e9, 4), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": round(ms_graph, 4), "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-            "config": {"workload": f"batching: {B} uint32 key-value instances, sizes log-uniform in [1K, 4M], "
-                                   f"uniform/normal/sorted/reverse keys, P=8", "instances": B, "total_keys": total,
-                       "P": P},
-            "eager_ms": round(ms_eager, 4), "graph_ms": round(ms_graph, 4),
-            "loop_ms": round(ms_loop, 4), "loop_wall_ms": round(wall_loop, 2),
-            "loop_GKeys_s": round(total / (ms_loop / 1e3) / 1e9, 4),
-            "speedup_vs_loop": round(ms_loop / ms_graph, 3)}
+            "value": b.pop("value"), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": b.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32", "data": "synthetic", "config": b.pop("config")}
+    line.update(b)
     print(json.dumps(line), flush=True)
 
 
@@ -412,15 +545,28 @@ def bench_serve(args):
     print("[bench] generating request pools", file=sys.stderr, flush=True)
     pools = [datagen.serve_pool_u64_torch(d, pool_n, 5, "cuda") for d in range(4)]
     torch.cuda.synchronize()
-    srv = S.Server(pools, P=64, budget_bytes=64 << 30, streams=4)
+    import numpy as np
+    from paper_1611_00463_amd import lbsort as L
     warm = S.make_requests(64, seed=55, pool_n=pool_n, rate=args.serve_rate, lo=10_000, hi=pool_n)
-    srv.run(warm)
+    S.Server(pools, P=64, budget_bytes=64 << 30, streams=4).run(warm)
     print(f"[bench] serving {args.serve_requests} requests at {args.serve_rate} req/s", file=sys.stderr, flush=True)
     reqs = S.make_requests(args.serve_requests, seed=5, pool_n=pool_n, rate=args.serve_rate, lo=10_000, hi=pool_n)
+    # a seeded sample of the requests keeps its outputs for the check below
+    kept = set(int(x) for x in np.random.default_rng(5).choice(len(reqs), min(16, len(reqs)), replace=False))
+    srv = S.Server(pools, P=64, budget_bytes=64 << 30, streams=4, keep_ids=kept)
     t0 = time.perf_counter()
     srv.run(reqs)
     wall = time.perf_counter() - t0
     served = S.summarize(reqs, wall)
+    assert served["device_errors"] == 0, "a served batch latched a device error"
+    for r in reqs:
+        if r.rid in kept:
+            alone = L.sort_keys(pools[r.dist][r.offset:r.offset + r.n], 64)
+            L.check(alone.workspace)
+            assert torch.equal(alone.keys.view(torch.int64), r.keys_out.view(torch.int64)), f"request {r.rid}"
+            assert torch.equal(alone.part_offsets[0], r.part_offsets), f"request {r.rid} offsets"
+            r.keys_out = r.part_offsets = None
+    served["checked"] = f"{len(kept)} sampled requests equal to the same request sorted alone"
     offered = sum(r.n for r in reqs) / max(r.arrival for r in reqs) / 1e9
     print("[bench] per-request baseline", file=sys.stderr, flush=True)
     base = S.make_requests(args.serve_requests, seed=5, pool_n=pool_n, rate=args.serve_rate, lo=10_000, hi=pool_n)
@@ -444,6 +590,94 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def measure_sort(w, args, steps, warmup, profile=True):
+    """Time one sort workload: `steps` steps without instrumentation (the
+    figure), then, with profile, `steps` more with per-launch events."""
+    import numpy as np
+    import torch
+    from paper_1611_00463_amd import lbsort as L
+    dev = torch.device("cuda:0")
+    lib = L.load()
+    print(f"[bench] generating {w['n']} keys ({w['tag']})", file=sys.stderr, flush=True)
+    keys, vals = make_input(w, dev)
+    kout = torch.empty_like(keys)
+    has_v = bool(w["vals"])
+    vout = torch.empty(w["n"], dtype=torch.uint32, device=dev) if has_v else None
+    ws = L.Workspace(dev)
+
+    def step():
+        if not has_v:
+            return L.sort_keys(keys, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
+                               keys_out=kout, workspace=ws)
+        return L.sort_pairs(keys, vals, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
+                            keys_out=kout, vals_out=vout, workspace=ws)
+
+    for _ in range(warmup):
+        r = step()
+    torch.cuda.synchronize()
+    L.check(ws.buf)
+    print(f"[bench] warmup done; timing {steps} steps", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        r = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    L.check(ws.buf)
+    prof, ms_prof = None, None
+    if profile:
+        lib.lbsort_profile_enable(1)
+        profile_read(lib)
+        e0.record(stream)
+        for _ in range(steps):
+            r = step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lib.lbsort_profile_enable(0)
+        prof = profile_read(lib)
+        ms_prof = e0.elapsed_time(e1) / steps
+        L.check(ws.buf)
+    counts = r.part_counts.cpu().numpy()[0].astype(np.float64)
+    imb = {"max_over_mean": round(float(counts.max() / counts.mean()), 6), "min": int(counts.min()),
+           "max": int(counts.max()), "P": w["P"]}
+    used = L.resolve_params(L.key_code(keys.dtype), (L.VAL_U32 if vals is not None else L.VAL_INDEX) if has_v
+                            else L.NOVAL, w["P"], w["n"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile)
+    out = dict(ms=ms, value=w["n"] / (ms / 1e3) / 1e9, prof=prof, ms_prof=ms_prof, imbalance=imb, settings=used,
+               kb=keys.element_size(), vb=4 if has_v else 0, dtype=KEY_NAMES[str(keys.dtype)])
+    del keys, vals, kout, vout, ws, r
+    torch.cuda.empty_cache()
+    return out
+
+
+def summarize_sort(w, m, steps):
+    """Kernel split, the dominant kernel's roofline and the pipeline's bytes."""
+    n, kb, vb, prof, value = w["n"], m["kb"], m["vb"], m["prof"], m["value"]
+    kernels = {k: {"launches_per_step": c / steps, "avg_ms": round(t / c, 5), "ms_per_step": round(t / steps, 5)}
+               for k, (c, t) in prof.items()}
+    dom = max(((k, t) for k, (c, t) in prof.items() if kernel_bytes_per_launch(k, n, kb, vb)), key=lambda x: x[1])[0]
+    c, t = prof[dom]
+    per_launch = kernel_bytes_per_launch(dom, n, kb, vb)
+    achieved = per_launch / (t / c / 1e3) / 1e9
+    tr = measured_traffic(dom, w["tag"])
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["bytes"] if tr else None,
+            "bytes_per_launch": per_launch, "avg_launch_ms": round(t / c, 5)}
+    if tr:
+        roof["traffic_detail"] = tr
+    ex = executed_bytes(prof, steps, lambda name: n, kb, vb) / n
+    D = kb  # one 8-bit digit pass per key byte
+    model_bytes = (kb + vb) * (2 * D + 2) + kb
+    pipe = {"executed_bytes_per_key": round(ex, 2), "executed_GBs": round(value * ex, 1),
+            "executed_frac": round(value * ex / HBM_PEAK_GBS, 4),
+            "model_bytes_per_key": model_bytes, "model_frac": round(value * model_bytes / HBM_PEAK_GBS, 4),
+            "note": "executed: algorithmic bytes of the kernels the step launched (histogram, radix passes, "
+                    "group fix-up, merge passes); model: the fixed normalisation (K+V)(2D+2)+K of an eight-pass "
+                    "LSD sort and one merge pass, which credits the radix passes the fix-up makes unnecessary"}
+    return roof, pipe, kernels
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,7 +685,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch", "serve", "balance", "search"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 25)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: leave out the duplicate-heavy and batched objects")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys of the all-cores oracle sample")
+    ap.add_argument("--cpu-sample-one", type=int, default=1 << 24, help="keys of the one-thread oracle sample")
     ap.add_argument("--fanin", type=int, default=0)
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--batch", type=int, default=4096, help="instances for --workload batch")
@@ -466,9 +703,7 @@ def main():
               f"exchange (the distributed form is a design note only)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_1611_00463_amd import lbsort as L
 
     if args.copy_calibration:
         a = torch.ones(args.copy_calibration // 8, dtype=torch.int64, device="cuda")
@@ -488,80 +723,40 @@ def main():
     if args.workload == "search":
         return bench_search(args)
     w = WORKLOADS[args.workload]
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    lib = L.load()
-    print(f"[bench] generating {w['n']} keys ({args.workload})", file=sys.stderr, flush=True)
-    keys, vals = make_input(w, dev)
-    kout = torch.empty_like(keys)
-    has_v = bool(w["vals"])
-    vout = torch.empty(w["n"], dtype=torch.uint32, device=dev) if has_v else None
-    ws = L.Workspace(dev)
-    kb, vb = keys.element_size(), 4 if has_v else 0
-
-    def step():
-        if not has_v:
-            return L.sort_keys(keys, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
-                               keys_out=kout, workspace=ws)
-        return L.sort_pairs(keys, vals, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
-                            keys_out=kout, vals_out=vout, workspace=ws)
-
-    for _ in range(args.warmup):
-        r = step()
-    torch.cuda.synchronize()
-    L.check(ws.buf)
-    print(f"[bench] warmup done; timing {args.steps} steps", file=sys.stderr, flush=True)
-    lib.lbsort_profile_enable(1)
-    profile_read(lib)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        r = step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    lib.lbsort_profile_enable(0)
-    ms = e0.elapsed_time(e1) / args.steps
-    prof = profile_read(lib)
-    L.check(ws.buf)
-
-    n = w["n"]
-    value = n / (ms / 1e3) / 1e9
-    counts = r.part_counts.cpu().numpy()[0].astype(np.float64)
-    imb = {"max_over_mean": round(float(counts.max() / counts.mean()), 6), "min": int(counts.min()),
-           "max": int(counts.max()), "P": w["P"]}
-    kernels = {k: {"launches_per_step": c / args.steps, "avg_ms": round(t / c, 5), "ms_per_step": round(t / args.steps, 5)}
-               for k, (c, t) in prof.items()}
-    dom = max(((k, t) for k, (c, t) in prof.items() if kernel_bytes_per_launch(k, n, kb, vb)), key=lambda x: x[1])[0]
-    c, t = prof[dom]
-    per_launch = kernel_bytes_per_launch(dom, n, kb, vb)
-    achieved = per_launch / (t / c / 1e3) / 1e9
-    D = kb  # one 8-bit digit pass per key byte
-    model_bytes = (kb + vb) * (2 * D + 2) + kb
-    tr = measured_traffic(dom, w["tag"])
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["bytes"] if tr else None,
-            "bytes_per_launch": per_launch, "avg_launch_ms": round(t / c, 5)}
-    if tr:
-        roof["traffic_detail"] = tr
+    cpu = None
+    if not args.no_cpu:
+        # before the GPU is touched: the oracle's worker processes start from a
+        # process that has not initialised the device
+        print("[bench] timing the CPU oracle on samples", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, min(args.cpu_sample, w["n"]), min(args.cpu_sample_one, w["n"]))
+    torch.cuda.set_device(torch.device("cuda:0"))
+    m = measure_sort(w, args, args.steps, args.warmup)
+    roof, pipe, kernels = summarize_sort(w, m, args.steps)
     line = {
-        "metric": METRIC, "value": round(value, 4), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": KEY_NAMES[str(keys.dtype)], "data": "synthetic",
-        "config": {"workload": w["desc"], "n": n, "P": w["P"], "s": w["s"], "key": KEY_NAMES[str(keys.dtype)],
+        "metric": METRIC, "value": round(m["value"], 4), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(m["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": m["dtype"], "data": "synthetic",
+        "config": {"workload": w["desc"], "n": w["n"], "P": w["P"], "s": w["s"], "key": m["dtype"],
                    "value": {True: "u32", "index": "u32 index (generated)", False: None}[w["vals"]],
-                   "investigator": "COUNT",
-                   "fanin": args.fanin or "tuned", "merge_tile": args.merge_tile or "tuned"},
-        "imbalance": imb,
+                   "investigator": "COUNT", "fanin": m["settings"]["fanin"],
+                   "merge_tile": m["settings"]["merge_tile"], "radix_tile": m["settings"]["radix_tile"]},
+        "imbalance": m["imbalance"],
         "roofline": roof,
-        "pipeline": {"bytes_per_key_model": model_bytes, "achieved_GBs": round(value * model_bytes, 1),
-                     "frac": round(value * model_bytes / HBM_PEAK_GBS, 4)},
+        "pipeline": pipe,
+        "profiled_ms_per_step": round(m["ms_prof"], 4),
         "kernels": kernels,
     }
-    if not args.no_cpu:
-        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n))
+    if args.workload == "pairs" and not args.no_extras:
+        wd = WORKLOADS["dups"]
+        md = measure_sort(wd, args, max(3, args.steps // 2), 1)
+        rd, pd, _ = summarize_sort(wd, md, max(3, args.steps // 2))
+        line["dups"] = {"workload": wd["desc"], "value": round(md["value"], 4), "unit": "GKeys/s",
+                        "ms_per_step": round(md["ms"], 4), "imbalance": md["imbalance"],
+                        "roofline": {k: rd[k] for k in ("kernel", "achieved", "frac", "avg_launch_ms")},
+                        "pipeline": {k: pd[k] for k in ("executed_bytes_per_key", "executed_frac", "model_frac")}}
+        line["batched"] = run_batch(args, max(3, args.steps // 2), 1)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

@@ -99,6 +99,8 @@ typedef struct lbsort_params {
   uint32_t investigator; /* LBSORT_INV_*                                                     */
   uint32_t fanin;        /* handler merge fan-in F per pass: 0 = tuned, else 2, 4, 8 or 16   */
   uint32_t merge_tile;   /* elements per merge tile: 0 = tuned, else 1024, 2048 or 4096     */
+  uint32_t radix_tile;   /* keys per radix tile of the local sort: 0 = tuned, else 4096 or
+                            8192 (digits are 8 bits wide in every case)                     */
   uint32_t reserved;     /* must be 0                                                        */
 } lbsort_params;
 
@@ -229,18 +231,42 @@ const char *lbsort_status_string(int status);
 const char *lbsort_last_error(void);
 
 /*
- * Measure the candidate (fan-in, merge tile) settings for one shape on the
- * current device and record the fastest in the tuning cache (host JSON file
- * at `cache_path`, or $LBSORT_TUNE_CACHE, or no file if both are NULL/empty).
- * Allocates its own scratch device memory.  n is the instance size; B > 1
- * tunes the batched form with B instances of n keys.  On success the chosen
- * fan-in and tile are stored to *fanin / *merge_tile (host, may be NULL).
+ * Autotuner (Section IV.C's several data sets at once, sorted with settings
+ * picked by measurement).  Times candidate settings of one batched shape on
+ * the current device and records the fastest in the tuning cache, keyed by
+ * the device architecture, the key width, values or not, the instance size
+ * (total_n / B, to a power of two), batched or not, and P.  Searched: the
+ * radix tile (4096, 8192) and the handler fan-in F (2 .. 16, at most the
+ * power of two above P) with the default merge tile, then the merge tile
+ * (1024, 2048, 4096) with the best of those.  Every candidate must produce
+ * the same bytes (keys, values, part_offsets) as the first, else
+ * LBSORT_ERR_DEVICE.  The radix digit is 8 bits wide in every case.
+ *
+ * keys_in / vals_in / seg_offsets (device): the caller's batch, as for
+ * lbsort_sort_batch (seg_offsets may be NULL for B = 1); tuning on it leaves
+ * it unchanged.  keys_in == NULL: B synthetic instances of total_n / B
+ * uniform random keys instead.  The tuner allocates its own outputs and
+ * workspace (device memory) and frees them before returning; it synchronises.
+ * cache_path (host): JSON file the whole table is written to (NULL: the
+ * $LBSORT_TUNE_CACHE file, or none).  chosen (host, may be NULL) receives the
+ * winning settings.  Later calls with fanin / merge_tile / radix_tile = 0 on
+ * the same shape class use them.
  */
-int lbsort_autotune(int key_type, int val_type, uint64_t n, uint32_t B, uint32_t P,
-                    const char *cache_path, uint32_t *fanin, uint32_t *merge_tile);
+int lbsort_autotune(int key_type, int val_type, const void *keys_in, const void *vals_in,
+                    const uint64_t *seg_offsets, uint32_t B, uint64_t total_n, uint32_t P,
+                    const char *cache_path, lbsort_params *chosen);
 
 /* Load a tuning cache written by lbsort_autotune (host path). */
 int lbsort_load_tuning(const char *cache_path);
+
+/*
+ * The settings a sort call with these arguments would run with on the
+ * current device (host only, nothing enqueued): P, s (the default budget
+ * resolved), investigator, and fanin / merge_tile / radix_tile as given,
+ * else from the tuning cache, else the defaults.  out (host) receives them.
+ */
+int lbsort_resolve_params(int key_type, int val_type, uint32_t B, uint64_t total_n,
+                          const lbsort_params *params, lbsort_params *out);
 
 /*
  * Measurement aid.  While enabled (on != 0), every kernel launch of the sort

@@ -109,7 +109,7 @@ static u32 device_cus() {
 
 struct Shape {
   int key_type, val_type;
-  u32 B, P, s, inv, F, TM, L, D;
+  u32 B, P, s, inv, F, TM, L, D, rtile;
   u64 total_n;
   bool single;      // one instance whose size the host knows
   bool has_small, has_large;
@@ -187,7 +187,7 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
                 val_type);
   if (val_type == LBSORT_VAL_INDEX && B == 1 && total_n > (1ull << 32))
     return fail(LBSORT_ERR_UNSUPPORTED, "LBSORT_VAL_INDEX needs n <= 2^32 (32-bit positions)");
-  lbsort_params d = {1, 0, LBSORT_INV_COUNT, 0, 0, 0};
+  lbsort_params d = {1, 0, LBSORT_INV_COUNT, 0, 0, 0, 0};
   const lbsort_params& p = prm ? *prm : d;
   if (p.P < 1 || p.P > LBSORT_MAX_P) return fail(LBSORT_ERR_INVALID_ARG, "P must be in [1, %d] (got %u)", LBSORT_MAX_P, p.P);
   if (p.investigator > 2) return fail(LBSORT_ERR_INVALID_ARG, "unknown investigator mode %u", p.investigator);
@@ -196,6 +196,9 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
     return fail(LBSORT_ERR_INVALID_ARG, "fanin must be 0, 2, 4, 8 or 16 (got %u)", p.fanin);
   if (p.merge_tile != 0 && p.merge_tile != 1024 && p.merge_tile != 2048 && p.merge_tile != 4096)
     return fail(LBSORT_ERR_INVALID_ARG, "merge_tile must be 0, 1024, 2048 or 4096 (got %u)", p.merge_tile);
+  if (p.radix_tile != 0 && p.radix_tile != RTILE_SMALL && p.radix_tile != RTILE_LARGE)
+    return fail(LBSORT_ERR_INVALID_ARG, "radix_tile must be 0, %u or %u (got %u)", RTILE_SMALL, RTILE_LARGE,
+                p.radix_tile);
   if (p.reserved != 0) return fail(LBSORT_ERR_INVALID_ARG, "reserved must be 0");
   if (B < 1) return fail(LBSORT_ERR_INVALID_ARG, "B must be >= 1");
   if (total_n >= (1ull << 44)) return fail(LBSORT_ERR_UNSUPPORTED, "total_n must be < 2^44");
@@ -215,8 +218,7 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   sh.s = p.s ? p.s : (budget >= p.P ? budget / p.P * p.P : (budget > 0 ? budget : 1u));
   // merge fan-in and tile: explicit, else tuned, else defaults
   // tuned settings depend on the widths only
-  Tuned tu = tuning_lookup(kb == 8 ? LBSORT_U64 : LBSORT_U32, val_type ? LBSORT_VAL_U32 : LBSORT_NOVAL, total_n / B, B,
-                           p.P);
+  Tuned tu = tuning_lookup(kb, val_type != LBSORT_NOVAL, total_n / B, B, p.P);
   u32 F = p.fanin ? p.fanin : tu.fanin;
   if (!F) {
     F = 2;
@@ -225,6 +227,7 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   }
   sh.F = F;
   sh.TM = p.merge_tile ? p.merge_tile : (tu.merge_tile ? tu.merge_tile : 2048u);
+  sh.rtile = p.radix_tile ? p.radix_tile : (tu.radix_tile ? tu.radix_tile : RTILE_LARGE);
   u32 L = 0;
   for (u64 span = 1; span < p.P; span *= F) ++L;
   sh.L = local_only ? 0 : L;
@@ -239,7 +242,7 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
       if (n >= (1ull << 32)) return fail(LBSORT_ERR_UNSUPPORTED, "a block of 2^32 keys or more (raise P)");
       if (n > (u64)SMALL_TILE) {
         sh.has_large = true;
-        sh.max_tiles += (n + SORT_TILE - 1) / SORT_TILE;
+        sh.max_tiles += (n + sh.rtile - 1) / sh.rtile;
       } else if (n > 0) {
         sh.has_small = true;
       }
@@ -247,7 +250,7 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
     }
   } else {
     sh.has_small = sh.has_large = true;
-    sh.max_tiles = total_n / SORT_TILE + NB;
+    sh.max_tiles = total_n / sh.rtile + NB;
     const u64 cap = NB * sh.s;
     sh.max_samples = total_n < cap ? total_n : cap;
   }
@@ -273,6 +276,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.L = sh.L;
   p.TM = sh.TM;
   p.max_tiles = (u32)sh.max_tiles;
+  p.rtile = sh.rtile;
   p.nq = NQ;
   p.persist_wgs = device_cus() * 4;
   p.total_n = sh.total_n;
@@ -539,6 +543,17 @@ int lbsort_sort_batch(int key_type, int val_type, const void* keys_in, const voi
   if (rc) return rc;
   if (!seg_offsets) return fail(LBSORT_ERR_INVALID_ARG, "seg_offsets must not be NULL");
   return dispatch(sh, keys_in, vals_in, keys_out, vals_out, seg_offsets, parts, ws, ws_bytes, stream);
+}
+
+int lbsort_resolve_params(int key_type, int val_type, uint32_t B, uint64_t total_n, const lbsort_params* params,
+                          lbsort_params* out) {
+  if (!out) return fail(LBSORT_ERR_INVALID_ARG, "out must not be NULL");
+  Shape sh;
+  int rc = make_shape(key_type, val_type, B, total_n, params, false, sh);
+  if (rc) return rc;
+  lbsort_params r = {sh.P, sh.s, sh.inv, sh.F, sh.TM, sh.rtile, 0};
+  *out = r;
+  return LBSORT_OK;
 }
 
 int lbsort_local_sort(int key_type, int val_type, const void* keys_in, const void* vals_in, void* keys_out,

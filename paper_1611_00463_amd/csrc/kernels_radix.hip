@@ -88,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
     // with a filter, only the listed large blocks are planned (small blocks
     // and sample offsets are unaffected by it)
     const bool keep = p.only == nullptr || (idx < p.NB && p.only[idx] != 0);
-    const u64 tiles = (keep && n > (u64)SMALL_TILE) ? (n + SORT_TILE - 1) / SORT_TILE : 0;
+    const u64 tiles = (keep && n > (u64)SMALL_TILE) ? (n + p.rtile - 1) / p.rtile : 0;
     const u64 smp = n < (u64)p.s ? n : (u64)p.s;
     const u64 small = (p.only == nullptr && n > 0 && n <= (u64)SMALL_TILE) ? 1 : 0;
     u64 tot;
@@ -168,12 +168,12 @@ __global__ __launch_bounds__(256) void k_tile_desc(Plan p) {
     const u32 blk = p.large_list[x + p.nq * jx];
     TileDesc d;
     d.bstart = p.blk_start[blk];
-    d.tbase = d.bstart + (u64)lt * SORT_TILE;
+    d.tbase = d.bstart + (u64)lt * p.rtile;
     const u64 rem = p.blk_start[blk + 1] - d.tbase;
     d.blk = blk;
     d.lt = lt;
     d.jx = jx;
-    d.tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+    d.tile_n = rem < (u64)p.rtile ? (u32)rem : p.rtile;
     d.tail = Q.nb * Q.rmin + Q.rem(jx) - Q.rmin;
     d.pad = 0;
     p.tdesc[g] = d;
@@ -225,14 +225,15 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
       while (t >= p.tstart[blk + 1]) ++blk;
       __syncthreads();
     }
-    const u64 tbase = p.blk_start[blk] + (u64)(t - p.tstart[blk]) * SORT_TILE;
+    const u64 tbase = p.blk_start[blk] + (u64)(t - p.tstart[blk]) * p.rtile;
     const u64 rem = p.blk_start[blk + 1] - tbase;
-    const u32 tile_n = rem < (u64)SORT_TILE ? (u32)rem : (u32)SORT_TILE;
+    const u32 tile_n = rem < (u64)p.rtile ? (u32)rem : p.rtile;
     // the tile's keys are read HB at a time, all loads in flight together
     // (a load and its use in one step made every key wait on memory alone)
     constexpr int HB = 8;
-    static_assert((SORT_TILE / SORT_NT) % HB == 0, "whole load batches");
-    for (int j0 = 0; j0 < SORT_TILE / SORT_NT; j0 += HB) {
+    static_assert((RTILE_SMALL / SORT_NT) % HB == 0 && (RTILE_LARGE / SORT_NT) % HB == 0, "whole load batches");
+    const int per_thread = (int)(p.rtile / SORT_NT);
+    for (int j0 = 0; j0 < per_thread; j0 += HB) {
     K kb[HB];
 #pragma unroll
     for (int u = 0; u < HB; ++u) {
@@ -390,7 +391,8 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
                                                  const u32* __restrict__ srcv0, K* __restrict__ dst0,
                                                  u32* __restrict__ dstv0, u32 pass) {
   constexpr int NWV = NT / 64, WI = 64 * ITEMS;
-  static_assert(NT * ITEMS == SORT_TILE, "tiles of SORT_TILE keys");
+  constexpr u32 TILE = NT * ITEMS;  // the launch passes this kernel only calls whose p.rtile == TILE
+  static_assert(TILE == RTILE_SMALL || TILE == RTILE_LARGE, "radix tiles of RTILE_SMALL or RTILE_LARGE keys");
   static_assert(NT >= RADIX, "one thread per digit");
   // LDS: 16-bit per-wave digit counters (they end up holding the tile-local
   // start of each wave's run of a digit), 32-bit block-relative write bases,
@@ -404,8 +406,8 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
     u64 scan[NWV];
     u32 gbase[RADIX];
     uint16_t wc[NWV][RADIX];
-    K stage[SORT_TILE];
-    u32 vstage[HASV ? SORT_TILE : 1];
+    K stage[TILE];
+    u32 vstage[HASV ? TILE : 1];
   };
   __shared__ Smem sm;
   auto& s_scan = sm.scan;
@@ -640,13 +642,11 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
 //    equal (heavy duplicates); a key of it that differs from its predecessor
 //    flags the block for k_group_fix_mid.
 constexpr u32 GF_SHIFT = 40;
-constexpr int GF_NT = 1024;
-constexpr u32 GF_WIN = SORT_TILE + 2 * GF_HALO;
 
-// The first fix-up works on parts of GF1_SPAN keys of a radix tile, so that
-// its LDS window is small enough for several workgroups per compute unit.
-constexpr u32 GF1_SPLIT = 2;
-constexpr u32 GF1_SPAN = SORT_TILE / GF1_SPLIT;
+// The fix-ups work on parts of GF1_SPAN keys of a radix tile (rtile /
+// GF1_SPAN parts per tile), so that their LDS window is small enough for
+// several workgroups per compute unit.
+constexpr u32 GF1_SPAN = RTILE_SMALL;
 constexpr int GF1_NT = 512;
 constexpr u32 GF1_WIN = GF1_SPAN + 2 * GF_HALO;
 
@@ -659,14 +659,15 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix(Plan p, const u64* __restr
   __shared__ u64 s_hb[NW];  // bit w: window position w starts a group
   __shared__ u32 s_blk;
   const u32 tid = threadIdx.x, lane = tid & 63;
-  const u32 t = blockIdx.x / GF1_SPLIT, part = blockIdx.x % GF1_SPLIT;  // radix tile and its part
+  const u32 split = p.rtile / GF1_SPAN;
+  const u32 t = blockIdx.x / split, part = blockIdx.x % split;  // radix tile and its part
   if (t >= p.tstart[p.NB]) return;
   if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t);
   for (u32 i = tid; i < NW; i += GF1_NT) s_hb[i] = 0;
   __syncthreads();
   const u32 blk = s_blk;
   const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
-  const u64 ts = bs + (u64)(t - p.tstart[blk]) * SORT_TILE + (u64)part * GF1_SPAN;
+  const u64 ts = bs + (u64)(t - p.tstart[blk]) * p.rtile + (u64)part * GF1_SPAN;
   if (ts >= be) return;  // the last tile of a block may not reach this part
   const u64 te = be - ts < (u64)GF1_SPAN ? be : ts + GF1_SPAN;
   const u64 ws = ts - bs > GF_HALO ? ts - GF_HALO : bs;
@@ -754,7 +755,7 @@ template <bool HASV>
 void launch_group_fix(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s) {
   if (p.max_tiles == 0) return;
   const int pe_ = prof_begin(s);
-  hipLaunchKernelGGL(k_group_fix<HASV>, dim3(p.max_tiles * GF1_SPLIT), dim3(GF1_NT), 0, s, p, src, srcv, dst, dstv);
+  hipLaunchKernelGGL(k_group_fix<HASV>, dim3(p.max_tiles * (p.rtile / GF1_SPAN)), dim3(GF1_NT), 0, s, p, src, srcv, dst, dstv);
   prof_end(pe_, "group_fix", s);
 }
 template void launch_group_fix<false>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
@@ -793,7 +794,8 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix_mid(Plan p, const u64* __r
   __shared__ u32 s_nmid, s_mbase, s_empty;
   __shared__ u32 s_blk;
   const u32 tid = threadIdx.x, lane = tid & 63;
-  const u32 t = blockIdx.x / GF1_SPLIT, part = blockIdx.x % GF1_SPLIT;  // radix tile and its part
+  const u32 split = p.rtile / GF1_SPAN;
+  const u32 t = blockIdx.x / split, part = blockIdx.x % split;  // radix tile and its part
   if (p.counters[C_ANYFLAG] == 0 || t >= p.tstart[p.NB]) return;  // no block flagged
   if (tid == 0) {
     s_blk = find_seg(p.tstart, p.NB, t);
@@ -805,7 +807,7 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix_mid(Plan p, const u64* __r
   const u32 blk = s_blk;
   if (p.gflags[blk] == 0) return;  // the first fix-up finished this block
   const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
-  const u64 ts = bs + (u64)(t - p.tstart[blk]) * SORT_TILE + (u64)part * GF1_SPAN;
+  const u64 ts = bs + (u64)(t - p.tstart[blk]) * p.rtile + (u64)part * GF1_SPAN;
   if (ts >= be) return;  // the last tile of a block may not reach this part
   const u64 te = be - ts < (u64)GF1_SPAN ? be : ts + GF1_SPAN;
   // inner window [ws, we) in LDS
@@ -1029,7 +1031,7 @@ template <bool HASV>
 void launch_group_fix_mid(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s) {
   if (p.max_tiles == 0) return;
   const int pe_ = prof_begin(s);
-  hipLaunchKernelGGL(k_group_fix_mid<HASV>, dim3(p.max_tiles * GF1_SPLIT), dim3(GF1_NT), 0, s, p, src, srcv, dst, dstv);
+  hipLaunchKernelGGL(k_group_fix_mid<HASV>, dim3(p.max_tiles * (p.rtile / GF1_SPAN)), dim3(GF1_NT), 0, s, p, src, srcv, dst, dstv);
   prof_end(pe_, "group_fix_mid", s);
 }
 template void launch_group_fix_mid<false>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
@@ -1337,19 +1339,30 @@ void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32
 template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s) {
   if (p.max_tiles == 0) return;
-  // Persistent grid: one 1024-thread workgroup (8 keys per thread) per
-  // compute unit, a multiple of the queue count.
-  constexpr int NT = SORT_TILE / 8;
+  // Persistent grid, 8 keys per thread: tiles of 8192 keys take one
+  // 1024-thread workgroup per compute unit (about 105 KB of LDS for 64-bit
+  // keys with values), tiles of 4096 keys two 512-thread workgroups; a
+  // multiple of the queue count.
+  const u32 NT = p.rtile / 8;
   u32 grid = p.persist_wgs * 256 / NT;
   grid = grid < p.max_tiles ? grid : p.max_tiles;
   grid = (grid + p.nq - 1) / p.nq * p.nq;
   const int pe_ = prof_begin(s);
-  if (p.only)
-    hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, 1, true>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst,
-                       dstv, pass);
-  else
-    hipLaunchKernelGGL((k_onesweep<K, HASV, NT, SORT_TILE / NT, 1, false>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst,
-                       dstv, pass);
+  if (p.rtile == RTILE_SMALL) {
+    if (p.only)
+      hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_SMALL / 8, 8, 2, true>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
+                         dst, dstv, pass);
+    else
+      hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_SMALL / 8, 8, 2, false>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
+                         dst, dstv, pass);
+  } else {
+    if (p.only)
+      hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_LARGE / 8, 8, 1, true>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
+                         dst, dstv, pass);
+    else
+      hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_LARGE / 8, 8, 1, false>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
+                         dst, dstv, pass);
+  }
   prof_end(pe_, p.only ? "onesweep_fallback" : "onesweep", s);
 }
 

@@ -12,16 +12,15 @@ typedef uint64_t u64;
 
 // Radix sort geometry (step 1): 8-bit digits.  Blocks of at most SMALL_TILE
 // keys are sorted whole in LDS (SORT_NT threads x SORT_ITEMS keys); larger
-// blocks are cut into radix tiles of SORT_TILE keys.
-#ifndef LBS_RADIX_TILE
-#define LBS_RADIX_TILE 8192
-#endif
+// blocks are cut into radix tiles of Plan::rtile keys, RTILE_SMALL or
+// RTILE_LARGE (a call's choice, the same for all its passes).
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SORT_NT = 256;
 constexpr int SORT_ITEMS = 16;
 constexpr int SMALL_TILE = SORT_NT * SORT_ITEMS;  // 4096 keys
-constexpr int SORT_TILE = LBS_RADIX_TILE;
+constexpr u32 RTILE_SMALL = 4096;
+constexpr u32 RTILE_LARGE = 8192;
 constexpr int WAVE = 64;
 // Group fix-up of the 64-bit local sort: groups of at most GF_HALO keys are
 // ranked in place; in the blocks that have larger groups of different keys,
@@ -29,7 +28,6 @@ constexpr int WAVE = 64;
 // and sorted by a second kernel.
 constexpr u32 GF_HALO = 64;
 constexpr u32 GF_MID = 512;
-constexpr u32 GF_MIDPT = SORT_TILE / (GF_HALO + 1) + 1;  // listed groups starting in one radix tile, at most
 
 // Look-back status word: [63:56] epoch (pass + 1), [55:54] flag, [53:0] count.
 constexpr u64 ST_AGG = 1, ST_INC = 2;
@@ -80,6 +78,7 @@ struct Plan {
   u32 inv;               // investigator mode
   u32 F, L, TM;          // merge fan-in, merge levels, merge tile
   u32 max_tiles;         // radix tiles, worst case
+  u32 rtile;             // keys per radix tile: RTILE_SMALL or RTILE_LARGE
   u32 nq;                // radix tile queues (NQ, or 1)
   u32 persist_wgs;       // workgroups of the persistent radix pass
   u64 total_n;

@@ -1,7 +1,9 @@
-// Autotuner for the handler merge: picks the fan-in F and the merge tile per
-// shape by timing every candidate on the device, checks that every candidate
-// produced the same bytes, and keeps the winner in an in-process table that
-// can be saved to / loaded from a small JSON file.
+// Autotuner: picks the radix tile of the local sort, the handler's fan-in F
+// and its merge tile for one shape by timing the candidates on the device
+// (on the caller's own data, or on synthetic uniform instances), checks that
+// every candidate produced the same bytes as the first, and keeps the winner
+// in an in-process table keyed by the device architecture, which can be
+// saved to / loaded from a small JSON file.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -18,8 +20,8 @@
 namespace lbs {
 
 struct Entry {
-  int key_type, val_type;
-  uint32_t size_log2, batched, P, fanin, merge_tile;
+  std::string arch;  // e.g. "gfx950"
+  uint32_t key_bytes, values, size_log2, batched, P, fanin, merge_tile, radix_tile;
   double ms;
 };
 
@@ -33,6 +35,38 @@ static uint32_t size_class(uint64_t n) {
   return c;
 }
 
+static uint32_t key_bytes_of(int key_type) {
+  switch (key_type) {
+    case LBSORT_U32: case LBSORT_I32: case LBSORT_F32: return 4;
+    case LBSORT_U64: case LBSORT_I64: case LBSORT_F64: return 8;
+    default: return 0;
+  }
+}
+
+// Architecture name of the current device ("gfx950"), cached per device; ""
+// when there is no device.
+static std::string current_arch() {
+  constexpr int MAXD = 64;
+  static std::mutex mu;
+  static std::string names[MAXD];
+  static bool have[MAXD];
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXD) {
+    (void)hipGetLastError();
+    return "";
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!have[dev]) {
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) == hipSuccess) {
+      const std::string a = pr.gcnArchName;
+      names[dev] = a.substr(0, a.find(':'));
+    }
+    have[dev] = true;
+  }
+  return names[dev];
+}
+
 static int parse_file(const char* path, std::vector<Entry>& out) {
   FILE* f = fopen(path, "r");
   if (!f) return -1;
@@ -41,7 +75,8 @@ static int parse_file(const char* path, std::vector<Entry>& out) {
   size_t r;
   while ((r = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, r);
   fclose(f);
-  // One object per entry: {"key": .., "val": .., "size_log2": .., "batched": .., "P": .., "fanin": .., "merge_tile": .., "ms": ..}
+  // One object per entry: {"arch": "..", "key_bytes": .., "values": .., "size_log2": .., "batched": ..,
+  // "P": .., "fanin": .., "merge_tile": .., "radix_tile": .., "ms": ..}
   size_t pos = 0;
   while ((pos = s.find('{', pos + 1)) != std::string::npos) {
     size_t end = s.find('}', pos);
@@ -54,11 +89,22 @@ static int parse_file(const char* path, std::vector<Entry>& out) {
       v = strtod(obj.c_str() + p + pat.size(), nullptr);
       return true;
     };
-    double k, vt, sl, b, P, F, T, ms = 0;
-    if (num("key", k) && num("val", vt) && num("size_log2", sl) && num("batched", b) && num("P", P) &&
-        num("fanin", F) && num("merge_tile", T)) {
+    auto str = [&](const char* name, std::string& v) {
+      std::string pat = std::string("\"") + name + "\": \"";
+      size_t p = obj.find(pat);
+      if (p == std::string::npos) return false;
+      size_t q = obj.find('"', p + pat.size());
+      if (q == std::string::npos) return false;
+      v = obj.substr(p + pat.size(), q - p - pat.size());
+      return true;
+    };
+    std::string arch;
+    double kb, vt, sl, b, P, F, T, R, ms = 0;
+    if (str("arch", arch) && num("key_bytes", kb) && num("values", vt) && num("size_log2", sl) &&
+        num("batched", b) && num("P", P) && num("fanin", F) && num("merge_tile", T) && num("radix_tile", R)) {
       num("ms", ms);
-      out.push_back(Entry{(int)k, (int)vt, (uint32_t)sl, (uint32_t)b, (uint32_t)P, (uint32_t)F, (uint32_t)T, ms});
+      out.push_back(Entry{arch, (uint32_t)kb, (uint32_t)vt, (uint32_t)sl, (uint32_t)b, (uint32_t)P, (uint32_t)F,
+                          (uint32_t)T, (uint32_t)R, ms});
     }
     pos = end;
   }
@@ -72,10 +118,10 @@ static int write_file(const char* path) {
   for (size_t i = 0; i < g_table.size(); ++i) {
     const Entry& e = g_table[i];
     fprintf(f,
-            "  {\"key\": %d, \"val\": %d, \"size_log2\": %u, \"batched\": %u, \"P\": %u, \"fanin\": %u, "
-            "\"merge_tile\": %u, \"ms\": %.4f}%s\n",
-            e.key_type, e.val_type, e.size_log2, e.batched, e.P, e.fanin, e.merge_tile, e.ms,
-            i + 1 < g_table.size() ? "," : "");
+            "  {\"arch\": \"%s\", \"key_bytes\": %u, \"values\": %u, \"size_log2\": %u, \"batched\": %u, \"P\": %u, "
+            "\"fanin\": %u, \"merge_tile\": %u, \"radix_tile\": %u, \"ms\": %.4f}%s\n",
+            e.arch.c_str(), e.key_bytes, e.values, e.size_log2, e.batched, e.P, e.fanin, e.merge_tile, e.radix_tile,
+            e.ms, i + 1 < g_table.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -84,7 +130,7 @@ static int write_file(const char* path) {
 
 static void upsert(const Entry& e) {
   for (auto& x : g_table)
-    if (x.key_type == e.key_type && x.val_type == e.val_type && x.size_log2 == e.size_log2 &&
+    if (x.arch == e.arch && x.key_bytes == e.key_bytes && x.values == e.values && x.size_log2 == e.size_log2 &&
         x.batched == e.batched && x.P == e.P) {
       x = e;
       return;
@@ -92,7 +138,8 @@ static void upsert(const Entry& e) {
   g_table.push_back(e);
 }
 
-Tuned tuning_lookup(int key_type, int val_type, uint64_t n, uint32_t B, uint32_t P) {
+Tuned tuning_lookup(uint32_t key_bytes, bool values, uint64_t n, uint32_t B, uint32_t P) {
+  const std::string arch = current_arch();
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_env_loaded) {
     g_env_loaded = true;
@@ -103,21 +150,26 @@ Tuned tuning_lookup(int key_type, int val_type, uint64_t n, uint32_t B, uint32_t
         for (auto& e : v) upsert(e);
     }
   }
+  Tuned t = {0, 0, 0};
+  if (arch.empty()) return t;
   const uint32_t sc = size_class(n);
   const uint32_t batched = B > 1 ? 1 : 0;
   const Entry* best = nullptr;
   for (auto& e : g_table) {
-    if (e.key_type != key_type || e.val_type != val_type || e.batched != batched || e.P != P) continue;
+    if (e.arch != arch || e.key_bytes != key_bytes || e.values != (values ? 1u : 0u) || e.batched != batched ||
+        e.P != P)
+      continue;
     if (!best || (uint32_t)abs((int)e.size_log2 - (int)sc) < (uint32_t)abs((int)best->size_log2 - (int)sc)) best = &e;
   }
-  Tuned t = {0, 0};
   if (best && (uint32_t)abs((int)best->size_log2 - (int)sc) <= 2) {
     t.fanin = best->fanin;
     t.merge_tile = best->merge_tile;
+    t.radix_tile = best->radix_tile;
   }
   return t;
 }
 
+// Synthetic instances: SplitMix64 (Steele, Lea and Flood 2014) of the index.
 __global__ void k_gen(void* keys, uint32_t* vals, uint64_t n, int key64, uint64_t seed) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
@@ -128,6 +180,14 @@ __global__ void k_gen(void* keys, uint32_t* vals, uint64_t n, int key64, uint64_
     else ((uint32_t*)keys)[i] = (uint32_t)(z >> 32);
     if (vals) vals[i] = (uint32_t)i;
   }
+}
+
+// Number of 32-bit words that differ between a and b, added to *count.
+__global__ void k_diff(const uint32_t* a, const uint32_t* b, uint64_t words, unsigned long long* count) {
+  unsigned long long c = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+    c += a[i] != b[i] ? 1 : 0;
+  if (c) atomicAdd(count, c);
 }
 
 }  // namespace lbs
@@ -144,119 +204,168 @@ extern "C" int lbsort_load_tuning(const char* cache_path) {
   return LBSORT_OK;
 }
 
-extern "C" int lbsort_autotune(int key_type, int val_type, uint64_t n, uint32_t B, uint32_t P, const char* cache_path,
-                               uint32_t* fanin_out, uint32_t* tile_out) {
-  if ((key_type != LBSORT_U32 && key_type != LBSORT_U64) || (val_type != LBSORT_NOVAL && val_type != LBSORT_VAL_U32) ||
-      n == 0 || B == 0 || P < 1 || P > LBSORT_MAX_P)
+extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, const void* vals_in,
+                               const uint64_t* seg_offsets, uint32_t B, uint64_t total_n, uint32_t P,
+                               const char* cache_path, lbsort_params* chosen) {
+  const uint64_t kb = key_bytes_of(key_type);
+  if (!kb || (val_type != LBSORT_NOVAL && val_type != LBSORT_VAL_U32 && val_type != LBSORT_VAL_INDEX) ||
+      total_n == 0 || B == 0 || P < 1 || P > LBSORT_MAX_P)
     return LBSORT_ERR_INVALID_ARG;
-  const uint64_t kb = key_type == LBSORT_U64 ? 8 : 4;
-  const uint64_t total = n * B;
-  void *kin = nullptr, *kout = nullptr, *ref = nullptr, *ws = nullptr, *parts_mem = nullptr;
-  uint32_t *vin = nullptr, *vout = nullptr;
-  uint64_t* seg = nullptr;
-  int rc = LBSORT_OK;
-  std::vector<uint64_t> hseg(B + 1);
-  for (uint32_t b = 0; b <= B; ++b) hseg[b] = (uint64_t)b * n;
+  if (keys_in && B > 1 && !seg_offsets) return LBSORT_ERR_INVALID_ARG;
+  if (keys_in && val_type == LBSORT_VAL_U32 && !vals_in) return LBSORT_ERR_INVALID_ARG;
+  const std::string arch = current_arch();
+  if (arch.empty()) return LBSORT_ERR_HIP;
+  const bool hasv = val_type != LBSORT_NOVAL;
+  // candidates: radix tile and fan-in with the default merge tile first, then
+  // the merge tiles with the best of those
   std::vector<uint32_t> fans;
   for (uint32_t F : {2u, 4u, 8u, 16u}) {
     if (F > 2 && F / 2 >= P) break;
     fans.push_back(F);
   }
-  const uint32_t tiles[3] = {1024, 2048, 4096};
+  const uint32_t rtiles[2] = {4096, 8192}, mtiles[3] = {1024, 2048, 4096};
+  void *kin = nullptr, *kout = nullptr, *kref = nullptr, *ws = nullptr;
+  uint32_t *vin = nullptr, *vout = nullptr, *vref = nullptr;
+  uint64_t *seg = nullptr, *offs = nullptr, *oref = nullptr;
+  unsigned long long* diff = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t st = nullptr;
+  int rc = LBSORT_OK;
   size_t ws_need = 0;
   double best_ms = 1e30;
-  uint32_t best_f = 0, best_t = 0;
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  uint32_t best_f = 0, best_t = 0, best_r = 0;
+  bool have_ref = false;
   lbsort_parts parts;
   memset(&parts, 0, sizeof parts);
-  for (uint32_t F : fans)
-    for (uint32_t T : tiles) {
-      lbsort_params prm = {P, 0, LBSORT_INV_COUNT, F, T, 0};
-      size_t need = 0;
-      int r2 = lbsort_sort_batch(key_type, val_type, nullptr, nullptr, nullptr, nullptr, (const uint64_t*)1, B, total,
-                                 &prm, &parts, nullptr, &need, nullptr);
+  const uint64_t noffs = (uint64_t)B * (P + 1);
+  auto measure = [&](uint32_t R, uint32_t F, uint32_t T) -> int {
+    lbsort_params prm = {P, 0, LBSORT_INV_COUNT, F, T, R, 0};
+    size_t wsb = ws_need;
+    float times[5];
+    for (int it = 0; it < 6; ++it) {
+      if (hipEventRecord(e0, st) != hipSuccess) return LBSORT_ERR_HIP;
+      int r2 = lbsort_sort_batch(key_type, val_type, kin, vin, kout, vout, seg, B, total_n, &prm, &parts, ws, &wsb, st);
       if (r2) return r2;
-      ws_need = std::max(ws_need, need);
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return LBSORT_ERR_HIP;
+      if (it > 0 && hipEventElapsedTime(&times[it - 1], e0, e1) != hipSuccess) return LBSORT_ERR_HIP;
     }
-  if (hipMalloc(&kin, total * kb) || hipMalloc(&kout, total * kb) || hipMalloc(&ref, total * kb) ||
-      hipMalloc(&ws, ws_need) || hipMalloc(&seg, (B + 1) * 8) || hipMalloc(&parts_mem, (uint64_t)B * (P + 1) * 8) ||
-      (val_type && (hipMalloc(&vin, total * 4) || hipMalloc(&vout, total * 4)))) {
+    int dev = lbsort_check(ws, st);
+    if (dev) return dev;
+    if (!have_ref) {
+      if (hipMemcpyAsync(kref, kout, total_n * kb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          (hasv && hipMemcpyAsync(vref, vout, total_n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess) ||
+          hipMemcpyAsync(oref, offs, noffs * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return LBSORT_ERR_HIP;
+      have_ref = true;
+    } else {
+      // every candidate must produce the same bytes
+      unsigned long long nd = 0;
+      if (hipMemsetAsync(diff, 0, sizeof(unsigned long long), st) != hipSuccess) return LBSORT_ERR_HIP;
+      hipLaunchKernelGGL(k_diff, dim3(2048), dim3(256), 0, st, (const uint32_t*)kref, (const uint32_t*)kout,
+                         total_n * kb / 4, diff);
+      if (hasv)
+        hipLaunchKernelGGL(k_diff, dim3(2048), dim3(256), 0, st, (const uint32_t*)vref, (const uint32_t*)vout, total_n,
+                           diff);
+      hipLaunchKernelGGL(k_diff, dim3(64), dim3(256), 0, st, (const uint32_t*)oref, (const uint32_t*)offs, noffs * 2,
+                         diff);
+      if (hipMemcpyAsync(&nd, diff, sizeof nd, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return LBSORT_ERR_HIP;
+      if (nd) return LBSORT_ERR_DEVICE;
+    }
+    std::sort(times, times + 5);
+    if (times[2] < best_ms) {
+      best_ms = times[2];
+      best_f = F;
+      best_t = T;
+      best_r = R;
+    }
+    return LBSORT_OK;
+  };
+  for (uint32_t R : rtiles)
+    for (uint32_t F : fans)
+      for (uint32_t T : mtiles) {
+        lbsort_params prm = {P, 0, LBSORT_INV_COUNT, F, T, R, 0};
+        size_t need = 0;
+        parts.part_offsets = (uint64_t*)1;  // the size query reads no pointer
+        rc = lbsort_sort_batch(key_type, val_type, nullptr, nullptr, nullptr, nullptr, (const uint64_t*)1, B, total_n,
+                               &prm, &parts, nullptr, &need, nullptr);
+        if (rc) goto done;
+        ws_need = std::max(ws_need, need);
+      }
+  if (hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = LBSORT_ERR_HIP;
+    goto done;
+  }
+  if (hipMalloc(&kout, total_n * kb) || hipMalloc(&kref, total_n * kb) || hipMalloc(&ws, ws_need) ||
+      hipMalloc(&offs, noffs * 8) || hipMalloc(&oref, noffs * 8) || hipMalloc(&diff, sizeof(unsigned long long)) ||
+      (hasv && (hipMalloc(&vout, total_n * 4) || hipMalloc(&vref, total_n * 4)))) {
     rc = LBSORT_ERR_OOM;
     goto done;
   }
-  hipMemcpy(seg, hseg.data(), (B + 1) * 8, hipMemcpyHostToDevice);
-  hipLaunchKernelGGL(k_gen, dim3(4096), dim3(256), 0, nullptr, kin, vin, total, key_type == LBSORT_U64 ? 1 : 0,
-                     (uint64_t)0x51ed270b27ull);
-  parts.part_offsets = (uint64_t*)parts_mem;
-  {
-    bool have_ref = false;
+  if (keys_in) {
+    kin = (void*)keys_in;
+    vin = (uint32_t*)vals_in;
+  } else {
+    if (hipMalloc(&kin, total_n * kb) || (val_type == LBSORT_VAL_U32 && hipMalloc(&vin, total_n * 4))) {
+      rc = LBSORT_ERR_OOM;
+      goto done;
+    }
+    hipLaunchKernelGGL(k_gen, dim3(4096), dim3(256), 0, st, kin, vin, total_n, kb == 8 ? 1 : 0,
+                       (uint64_t)0x51ed270b27ull);
+  }
+  if (seg_offsets) {
+    seg = (uint64_t*)seg_offsets;
+  } else {
+    // equal instances (the last one takes the remainder)
+    std::vector<uint64_t> hseg(B + 1);
+    for (uint32_t b = 0; b < B; ++b) hseg[b] = (uint64_t)b * (total_n / B);
+    hseg[B] = total_n;
+    if (hipMalloc(&seg, (B + 1) * 8) ||
+        hipMemcpyAsync(seg, hseg.data(), (B + 1) * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = LBSORT_ERR_HIP;
+      goto done;
+    }
+  }
+  parts.part_offsets = offs;
+  for (uint32_t R : rtiles)
     for (uint32_t F : fans)
-      for (uint32_t T : tiles) {
-        lbsort_params prm = {P, 0, LBSORT_INV_COUNT, F, T, 0};
-        size_t wsb = ws_need;
-        float times[5];
-        for (int it = 0; it < 6; ++it) {
-          hipEventRecord(e0, nullptr);
-          int r2 = lbsort_sort_batch(key_type, val_type, kin, vin, kout, vout, seg, B, total, &prm, &parts, ws, &wsb,
-                                     nullptr);
-          hipEventRecord(e1, nullptr);
-          if (r2) {
-            rc = r2;
-            goto done;
-          }
-          hipEventSynchronize(e1);
-          if (it > 0) hipEventElapsedTime(&times[it - 1], e0, e1);
-        }
-        int dev = lbsort_check(ws, nullptr);
-        if (dev) {
-          rc = dev;
-          goto done;
-        }
-        std::sort(times, times + 5);
-        if (!have_ref) {
-          hipMemcpy(ref, kout, total * kb, hipMemcpyDeviceToDevice);
-          have_ref = true;
-        } else {
-          std::vector<char> a(total * kb), b(total * kb);
-          hipMemcpy(a.data(), ref, total * kb, hipMemcpyDeviceToHost);
-          hipMemcpy(b.data(), kout, total * kb, hipMemcpyDeviceToHost);
-          if (memcmp(a.data(), b.data(), total * kb) != 0) {
-            rc = LBSORT_ERR_DEVICE;
-            goto done;
-          }
-        }
-        if (times[2] < best_ms) {
-          best_ms = times[2];
-          best_f = F;
-          best_t = T;
-        }
-      }
+      if ((rc = measure(R, F, 2048)) != LBSORT_OK) goto done;
+  {
+    const uint32_t R = best_r, F = best_f;
+    for (uint32_t T : mtiles)
+      if (T != 2048 && (rc = measure(R, F, T)) != LBSORT_OK) goto done;
   }
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    upsert(Entry{key_type, val_type, size_class(n), B > 1 ? 1u : 0u, P, best_f, best_t, best_ms});
-    if (cache_path && *cache_path) write_file(cache_path);
-    else {
-      const char* env = getenv("LBSORT_TUNE_CACHE");
-      if (env && *env) write_file(env);
-    }
+    upsert(Entry{arch, (uint32_t)kb, hasv ? 1u : 0u, size_class(total_n / B), B > 1 ? 1u : 0u, P, best_f, best_t,
+                 best_r, best_ms});
+    const char* path = (cache_path && *cache_path) ? cache_path : getenv("LBSORT_TUNE_CACHE");
+    if (path && *path && write_file(path) != 0) rc = LBSORT_ERR_INVALID_ARG;
   }
-  if (fanin_out) *fanin_out = best_f;
-  if (tile_out) *tile_out = best_t;
+  if (chosen) {
+    lbsort_params c = {P, 0, LBSORT_INV_COUNT, best_f, best_t, best_r, 0};
+    *chosen = c;
+  }
 done:
-  hipDeviceSynchronize();
-  hipFree(kin);
+  if (st) hipStreamSynchronize(st);
+  if (!keys_in) {
+    hipFree(kin);
+    hipFree(vin);
+  }
+  if (!seg_offsets) hipFree(seg);
   hipFree(kout);
-  hipFree(ref);
+  hipFree(kref);
+  hipFree(vout);
+  hipFree(vref);
   hipFree(ws);
-  hipFree(seg);
-  hipFree(parts_mem);
-  if (vin) hipFree(vin);
-  if (vout) hipFree(vout);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  hipFree(offs);
+  hipFree(oref);
+  hipFree(diff);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (st) hipStreamDestroy(st);
   return rc;
 }
 

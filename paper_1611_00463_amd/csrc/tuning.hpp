@@ -1,4 +1,5 @@
-// Tuning cache: merge fan-in and merge tile per shape, chosen by measurement.
+// Tuning cache: handler fan-in, merge tile and radix tile per shape and
+// device architecture, chosen by measurement (lbsort_autotune).
 #pragma once
 #include <stdint.h>
 
@@ -7,9 +8,11 @@ namespace lbs {
 struct Tuned {
   uint32_t fanin;       // 0 = no entry
   uint32_t merge_tile;  // 0 = no entry
+  uint32_t radix_tile;  // 0 = no entry
 };
 
-// Entry for (key type, value type, instance size, instances, P); zeros if none.
-Tuned tuning_lookup(int key_type, int val_type, uint64_t n, uint32_t B, uint32_t P);
+// Entry for (architecture of the current device, key width, values or not,
+// instance size, batched or not, P); zeros if none.
+Tuned tuning_lookup(uint32_t key_bytes, bool values, uint64_t n, uint32_t B, uint32_t P);
 
 }  // namespace lbs

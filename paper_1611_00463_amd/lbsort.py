@@ -14,9 +14,7 @@ from dataclasses import dataclass
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# LBSORT_LIB may point at another build of the same library (e.g. a variant
-# compiled for comparison); by default the in-tree build is used.
-LIB_PATH = os.environ.get("LBSORT_LIB") or os.path.join(HERE, "_lib", "liblbsort.so")
+LIB_PATH = os.path.join(HERE, "_lib", "liblbsort.so")
 
 U32, U64, I32, I64, F32, F64 = 1, 2, 3, 4, 5, 6
 NOVAL, VAL_U32, VAL_INDEX = 0, 1, 2
@@ -29,7 +27,8 @@ _c_u64p = ctypes.POINTER(ctypes.c_uint64)
 
 class Params(ctypes.Structure):
     _fields_ = [("P", ctypes.c_uint32), ("s", ctypes.c_uint32), ("investigator", ctypes.c_uint32),
-                ("fanin", ctypes.c_uint32), ("merge_tile", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("fanin", ctypes.c_uint32), ("merge_tile", ctypes.c_uint32), ("radix_tile", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class Parts(ctypes.Structure):
@@ -41,7 +40,7 @@ class Parts(ctypes.Structure):
 EXPORTS = ("lbsort_sort_keys", "lbsort_sort_pairs", "lbsort_sort_batch", "lbsort_local_sort",
            "lbsort_check", "lbsort_status_string", "lbsort_last_error", "lbsort_autotune",
            "lbsort_load_tuning", "lbsort_profile_enable", "lbsort_profile_read", "lbsort_search",
-           "lbsort_provenance", "lbsort_sort_pairs_noalloc")
+           "lbsort_provenance", "lbsort_sort_pairs_noalloc", "lbsort_resolve_params")
 
 _lib = None
 
@@ -52,14 +51,14 @@ class LbsortError(RuntimeError):
         self.code = code
 
 
-def load(path: str = LIB_PATH):
-    """Load the HIP library; raise if it is not built."""
+def load():
+    """Load the in-tree HIP library; raise if it is not built."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(path):
-        raise RuntimeError(f"lbsort HIP library not built ({path}); run paper_1611_00463_amd.build")
-    lib = ctypes.CDLL(path)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"lbsort HIP library not built ({LIB_PATH}); run paper_1611_00463_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)
     pp, pa = ctypes.POINTER(Params), ctypes.POINTER(Parts)
     lib.lbsort_sort_keys.argtypes = [i32, vp, vp, u64, pp, pa, vp, sz, vp]
@@ -70,7 +69,8 @@ def load(path: str = LIB_PATH):
     lib.lbsort_status_string.argtypes = [i32]
     lib.lbsort_status_string.restype = ctypes.c_char_p
     lib.lbsort_last_error.restype = ctypes.c_char_p
-    lib.lbsort_autotune.argtypes = [i32, i32, u64, u32, u32, ctypes.c_char_p, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+    lib.lbsort_autotune.argtypes = [i32, i32, vp, vp, vp, u32, u64, u32, ctypes.c_char_p, pp]
+    lib.lbsort_resolve_params.argtypes = [i32, i32, u32, u64, pp, pp]
     lib.lbsort_load_tuning.argtypes = [ctypes.c_char_p]
     lib.lbsort_profile_enable.argtypes = [i32]
     lib.lbsort_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -134,8 +134,8 @@ class Workspace:
         return self.buf
 
 
-def _params(P, s, investigator, fanin, merge_tile):
-    return Params(P, s, investigator, fanin, merge_tile, 0)
+def _params(P, s, investigator, fanin, merge_tile, radix_tile=0):
+    return Params(P, s, investigator, fanin, merge_tile, radix_tile, 0)
 
 
 def _alloc_parts(B, P, kdt, device, want_send, want_cuts):
@@ -162,7 +162,7 @@ def _run(fn, args_before_ws, ws: Workspace | None, device):
 
 
 def sort_batch(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torch.Tensor | None = None,
-               s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0,
+               s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0,
                keys_out=None, vals_out=None, want_send=False, want_cuts=False,
                workspace: Workspace | None = None, index_values: bool = False) -> SortResult:
     """lbsort_sort_batch: seg_offsets is a device tensor of B+1 offsets (int64/uint64).
@@ -176,7 +176,7 @@ def sort_batch(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torc
         vals_out = torch.empty(n, dtype=torch.uint32, device=keys.device)
     vt = VAL_U32 if vals is not None else (VAL_INDEX if index_values else NOVAL)
     parts, offs, counts, spl, send, cuts = _alloc_parts(B, P, keys.dtype, keys.device, want_send, want_cuts)
-    prm = _params(P, s, investigator, fanin, merge_tile)
+    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile)
     args = (kc, vt, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
             _ptr(seg_offsets), B, n, ctypes.byref(prm), ctypes.byref(parts))
     buf = _run(lib.lbsort_sort_batch, args, workspace, keys.device)
@@ -185,20 +185,20 @@ def sort_batch(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torc
 
 def sort_keys(keys: torch.Tensor, P: int, s: int = 0, investigator: int = INV_COUNT, fanin: int = 0,
               merge_tile: int = 0, keys_out=None, want_send=False, want_cuts=False,
-              workspace: Workspace | None = None) -> SortResult:
+              workspace: Workspace | None = None, radix_tile: int = 0) -> SortResult:
     """lbsort_sort_keys on one array."""
     lib = load()
     kc = key_code(keys.dtype)
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
     parts, offs, counts, spl, send, cuts = _alloc_parts(1, P, keys.dtype, keys.device, want_send, want_cuts)
-    prm = _params(P, s, investigator, fanin, merge_tile)
+    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile)
     args = (kc, _ptr(keys), _ptr(keys_out), keys.numel(), ctypes.byref(prm), ctypes.byref(parts))
     buf = _run(lib.lbsort_sort_keys, args, workspace, keys.device)
     return SortResult(keys_out, None, offs, counts, spl, send, cuts, buf)
 
 
 def sort_pairs(keys: torch.Tensor, vals: torch.Tensor | None, P: int, s: int = 0, investigator: int = INV_COUNT,
-               fanin: int = 0, merge_tile: int = 0, keys_out=None, vals_out=None, want_send=False,
+               fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0, keys_out=None, vals_out=None, want_send=False,
                want_cuts=False, workspace: Workspace | None = None) -> SortResult:
     """lbsort_sort_pairs on one array of keys with uint32 values.  vals=None
     sorts with LBSORT_VAL_INDEX: vals_out receives every key's input position."""
@@ -210,7 +210,7 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor | None, P: int, s: int = 0
     if vals_out is None:
         vals_out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
     parts, offs, counts, spl, send, cuts = _alloc_parts(1, P, keys.dtype, keys.device, want_send, want_cuts)
-    prm = _params(P, s, investigator, fanin, merge_tile)
+    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile)
     args = (kc, VAL_U32 if vals is not None else VAL_INDEX, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
             keys.numel(), ctypes.byref(prm), ctypes.byref(parts))
     buf = _run(lib.lbsort_sort_pairs, args, workspace, keys.device)
@@ -271,12 +271,31 @@ def check(workspace_buf: torch.Tensor):
     _check(load().lbsort_check(ctypes.c_void_p(workspace_buf.data_ptr()), _stream()))
 
 
-def autotune(key_type: int, val_type: int, n: int, B: int, P: int, cache_path: str | None = None):
+def autotune(key_type: int, val_type: int, P: int, total_n: int = 0, B: int = 1, keys: torch.Tensor | None = None,
+             vals: torch.Tensor | None = None, seg_offsets: torch.Tensor | None = None,
+             cache_path: str | None = None) -> dict:
+    """lbsort_autotune: tune on the given batch (keys, vals, seg_offsets
+    device tensors; B and total_n taken from them) or, with keys=None, on B
+    synthetic uniform instances of total_n / B keys.  Returns the chosen
+    settings."""
     lib = load()
-    f, t = ctypes.c_uint32(0), ctypes.c_uint32(0)
-    _check(lib.lbsort_autotune(key_type, val_type, n, B, P, cache_path.encode() if cache_path else None,
-                               ctypes.byref(f), ctypes.byref(t)))
-    return f.value, t.value
+    if keys is not None:
+        total_n = keys.numel()
+        B = 1 if seg_offsets is None else seg_offsets.numel() - 1
+    out = Params()
+    _check(lib.lbsort_autotune(key_type, val_type, _ptr(keys), _ptr(vals), _ptr(seg_offsets), B, total_n, P,
+                               cache_path.encode() if cache_path else None, ctypes.byref(out)))
+    return {"fanin": out.fanin, "merge_tile": out.merge_tile, "radix_tile": out.radix_tile}
+
+
+def resolve_params(key_type: int, val_type: int, P: int, total_n: int, B: int = 1, s: int = 0,
+                   investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0) -> dict:
+    """lbsort_resolve_params: the settings a call of this shape would use."""
+    prm = Params(P, s, investigator, fanin, merge_tile, radix_tile, 0)
+    out = Params()
+    _check(load().lbsort_resolve_params(key_type, val_type, B, total_n, ctypes.byref(prm), ctypes.byref(out)))
+    return {"P": out.P, "s": out.s, "investigator": out.investigator, "fanin": out.fanin,
+            "merge_tile": out.merge_tile, "radix_tile": out.radix_tile}
 
 
 def load_tuning(cache_path: str):
@@ -295,7 +314,7 @@ class BatchPlan:
     """
 
     def __init__(self, keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torch.Tensor | None = None,
-                 s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0,
+                 s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0,
                  keys_out=None, vals_out=None):
         lib = load()
         self.keys, self.vals, self.seg = keys, vals, seg_offsets
@@ -305,7 +324,7 @@ class BatchPlan:
         self.vals_out = (torch.empty_like(vals) if vals_out is None else vals_out) if vals is not None else None
         (self._parts, self.part_offsets, self.part_counts, self.splitters, _, _) = _alloc_parts(
             self.B, P, keys.dtype, keys.device, False, False)
-        self._prm = _params(P, s, investigator, fanin, merge_tile)
+        self._prm = _params(P, s, investigator, fanin, merge_tile, radix_tile)
         self._args = (key_code(keys.dtype), VAL_U32 if vals is not None else NOVAL, _ptr(keys), _ptr(vals),
                       _ptr(self.keys_out), _ptr(self.vals_out), _ptr(seg_offsets), self.B, keys.numel(),
                       ctypes.byref(self._prm), ctypes.byref(self._parts))

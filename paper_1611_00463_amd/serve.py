@@ -39,6 +39,7 @@ class Request:
     dist: int
     offset: int
     t_done: float = -1.0
+    error: int = 0      # device error bits of the request's batch (0 = none)
     keys_out: torch.Tensor | None = None
     part_offsets: torch.Tensor | None = None
 
@@ -50,11 +51,15 @@ class _Batch:
     done: torch.cuda.Event
     bytes: int
     keep: list = field(default_factory=list)
+    err: torch.Tensor | None = None   # pinned host copy of the batch's device error word
 
 
 class Server:
     def __init__(self, pools: list[torch.Tensor], P: int = 64, s: int = 0, budget_bytes: int = 64 << 30,
-                 streams: int = 4, max_batch_keys: int = 1 << 28, max_batch: int = 512, keep_outputs=False):
+                 streams: int = 4, max_batch_keys: int = 1 << 28, max_batch: int = 512, keep_outputs=False,
+                 keep_ids=None):
+        """keep_outputs: keep a copy of every request's sorted keys and
+        partition offsets; keep_ids: only of the requests with these ids."""
         self.pools = pools
         self.P, self.s = P, s
         self.budget = budget_bytes
@@ -62,6 +67,7 @@ class Server:
         self.max_batch_keys = max_batch_keys
         self.max_batch = max_batch
         self.keep_outputs = keep_outputs
+        self.keep_ids = None if keep_ids is None else set(keep_ids)
         self.lib = L.load()
 
     def request_bytes(self, n: int) -> int:
@@ -79,11 +85,30 @@ class Server:
                                                          non_blocking=True)
             seg = torch.from_numpy(offs.astype(np.uint64)).pin_memory().to("cuda", non_blocking=True)
             res = L.sort_batch(keys, seg, self.P, s=self.s)
+            # the error word the sort latched (first word of its workspace),
+            # copied to host memory in stream order, read once the batch is done
+            err = torch.empty(1, dtype=torch.int32, pin_memory=True)
+            err.copy_(res.workspace[:4].view(torch.int32), non_blocking=True)
             done = torch.cuda.Event()
             done.record(stream)
-        b = _Batch(reqs, stream, done, sum(self.request_bytes(n) for n in sizes), keep=[keys, seg, res])
+        b = _Batch(reqs, stream, done, sum(self.request_bytes(n) for n in sizes), keep=[keys, seg, res], err=err)
         b.offs = offs
         return b
+
+    def _collect(self, b: _Batch, t: float):
+        """A finished batch: latency, device errors, and the copies of the kept
+        outputs.  The copies run on the batch's own stream: its buffers go back
+        to that stream's pool once the batch is dropped and may be reused by its
+        next batch, which is ordered after these copies."""
+        err = int(b.err[0])
+        with torch.cuda.stream(b.stream):
+            for k, r in enumerate(b.reqs):
+                r.t_done = t
+                r.error = err
+                if self.keep_outputs or (self.keep_ids is not None and r.rid in self.keep_ids):
+                    a, e = int(b.offs[k]), int(b.offs[k + 1])
+                    r.keys_out = b.keep[2].keys[a:e].clone()
+                    r.part_offsets = b.keep[2].part_offsets[k].clone()
 
     def run(self, requests: list[Request], verbose=False):
         """Serve the requests in real time; returns them with t_done filled in."""
@@ -104,17 +129,7 @@ class Server:
             for si in list(inflight):
                 b = inflight[si]
                 if b.done.query():
-                    t = time.perf_counter() - t0
-                    # copies on the batch's own stream: its buffers go back to
-                    # that stream's pool below and may be reused by its next
-                    # batch, which is ordered after these copies
-                    with torch.cuda.stream(b.stream):
-                        for k, r in enumerate(b.reqs):
-                            r.t_done = t
-                            if self.keep_outputs:
-                                a, e = int(b.offs[k]), int(b.offs[k + 1])
-                                r.keys_out = b.keep[2].keys[a:e].clone()
-                                r.part_offsets = b.keep[2].part_offsets[k].clone()
+                    self._collect(b, time.perf_counter() - t0)
                     used -= b.bytes
                     n_done += len(b.reqs)
                     del inflight[si]
@@ -175,4 +190,5 @@ def summarize(reqs: list[Request], wall: float) -> dict:
     keys = sum(r.n for r in reqs)
     return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3), "GKeys_s": round(keys / wall / 1e9, 4),
-            "requests": len(reqs), "keys": int(keys), "wall_s": round(wall, 3)}
+            "requests": len(reqs), "keys": int(keys), "wall_s": round(wall, 3),
+            "device_errors": sum(1 for r in reqs if r.error)}

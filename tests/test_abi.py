@@ -40,7 +40,8 @@ def test_status_strings(lib):
 
 
 def _size(key_type=L.U64, P=8, n=1000, **kw):
-    prm = L.Params(P, kw.get("s", 0), kw.get("inv", 0), kw.get("fanin", 0), kw.get("tile", 0), kw.get("reserved", 0))
+    prm = L.Params(P, kw.get("s", 0), kw.get("inv", 0), kw.get("fanin", 0), kw.get("tile", 0), kw.get("rtile", 0),
+                   kw.get("reserved", 0))
     parts = L.Parts(1, 0, 0, 0, 0)
     need = ctypes.c_size_t(0)
     rc = L.load().lbsort_sort_keys(key_type, None, None, n, ctypes.byref(prm), ctypes.byref(parts), None,
@@ -64,6 +65,8 @@ def test_workspace_query_and_growth(lib):
     (dict(inv=9), L.ERR_INVALID_ARG),
     (dict(fanin=3), L.ERR_INVALID_ARG),
     (dict(tile=1000), L.ERR_INVALID_ARG),
+    (dict(rtile=1000), L.ERR_INVALID_ARG),
+    (dict(rtile=2048), L.ERR_INVALID_ARG),
     (dict(reserved=1), L.ERR_INVALID_ARG),
     (dict(s=(1 << 20) + 1), L.ERR_INVALID_ARG),
     (dict(n=1 << 45), L.ERR_UNSUPPORTED),
@@ -138,3 +141,40 @@ def test_search_and_provenance_argument_checks(lib):
     assert lib.lbsort_provenance(p, 5, 10, 0, p, p, None) == L.ERR_INVALID_ARG
     assert lib.lbsort_provenance(p, 5, (1 << 32) + 1, 4, p, p, None) == L.ERR_UNSUPPORTED
     assert lib.lbsort_provenance(p, 5, 10, 4, None, None, None) == L.ERR_INVALID_ARG
+
+
+def test_resolve_params_defaults_and_explicit(lib):
+    """Without a tuned entry (no device here) the defaults: F = 8 for P > 16,
+    else the power of two reaching P (at most 16); merge tile 2048; radix tile
+    8192; s = the paper's budget.  Explicit settings pass through."""
+    r = L.resolve_params(L.U64, L.VAL_U32, 64, 1 << 28)
+    assert r == {"P": 64, "s": 512, "investigator": 0, "fanin": 8, "merge_tile": 2048, "radix_tile": 8192}
+    assert L.resolve_params(L.U32, L.VAL_U32, 8, 1 << 20, B=4096)["fanin"] == 8
+    assert L.resolve_params(L.U64, L.NOVAL, 5, 1000)["fanin"] == 8
+    assert L.resolve_params(L.U64, L.NOVAL, 3, 1000)["fanin"] == 4
+    r = L.resolve_params(L.F64, L.VAL_INDEX, 10, 10 ** 6, s=7, investigator=2, fanin=4, merge_tile=1024,
+                         radix_tile=4096)
+    assert r == {"P": 10, "s": 7, "investigator": 2, "fanin": 4, "merge_tile": 1024, "radix_tile": 4096}
+    with pytest.raises(L.LbsortError):
+        L.resolve_params(L.U64, L.NOVAL, 8, 100, radix_tile=5)
+
+
+def test_radix_tile_sizes_the_workspace(lib):
+    """Smaller radix tiles need more look-back status words."""
+    def need(rt):
+        prm = L.Params(8, 0, 0, 0, 0, rt, 0)
+        parts = L.Parts(1, 0, 0, 0, 0)
+        n = ctypes.c_size_t(0)
+        assert lib.lbsort_sort_keys(L.U64, None, None, 1 << 22, ctypes.byref(prm), ctypes.byref(parts), None,
+                                    ctypes.byref(n), None) == 0
+        return n.value
+    assert need(4096) > need(8192) == need(0)
+
+
+def test_autotune_argument_checks(lib):
+    # rejected before any device work
+    assert lib.lbsort_autotune(7, 0, None, None, None, 1, 100, 8, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_autotune(L.U64, 0, None, None, None, 1, 0, 8, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_autotune(L.U64, 0, None, None, None, 0, 100, 8, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_autotune(L.U64, 0, ctypes.c_void_p(256), None, None, 2, 100, 8, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_autotune(L.U64, 1, ctypes.c_void_p(256), None, None, 1, 100, 8, None, None) == L.ERR_INVALID_ARG

@@ -13,7 +13,7 @@ import torch
 from oracle import sample_sort as O
 from paper_1611_00463_amd import datagen
 from paper_1611_00463_amd import lbsort as L
-from tests.parity import check_case, compare, to_dev, to_host, u64
+from tests.parity import check_case, compare, run_gpu, to_dev, to_host, u64
 
 pytestmark = pytest.mark.gpu
 
@@ -72,12 +72,13 @@ def test_all_equal_and_sorted_inputs(ws):
     check_case(k32, None, 10, 0, ws=ws)
 
 
+@pytest.mark.parametrize("rtile", [4096, 8192])
 @pytest.mark.parametrize("fanin", [2, 4, 8, 16])
 @pytest.mark.parametrize("tile", [1024, 2048, 4096])
-def test_tuning_settings_do_not_change_bytes(ws, fanin, tile):
+def test_tuning_settings_do_not_change_bytes(ws, fanin, tile, rtile):
     n = 700_001
     keys = datagen.duplicate_heavy_keys(n, seed=11)
-    check_case(keys, datagen.index_values(n), 37, 64, fanin=fanin, tile=tile, ws=ws)
+    check_case(keys, datagen.index_values(n), 37, 64, fanin=fanin, tile=tile, ws=ws, rtile=rtile)
 
 
 def test_local_sort_stage(ws):
@@ -147,8 +148,9 @@ def _top_small_keys(n, seed, top_values):
     return (np.asarray(top_values, dtype=np.uint64)[pick] << np.uint64(40)) | low
 
 
+@pytest.mark.parametrize("rtile", [0, 4096])
 @pytest.mark.parametrize("case", ["all_below_2_40", "half_blocks", "medium_groups", "small_groups", "clustered_f64"])
-def test_local_sort_group_paths(ws, case):
+def test_local_sort_group_paths(ws, case, rtile):
     n, P = 1_000_000, 8
     if case == "all_below_2_40":          # one group per block with distinct keys: every block falls back
         keys = datagen.uniform_keys(n, seed=41) >> np.uint64(24)
@@ -164,7 +166,7 @@ def test_local_sort_group_paths(ws, case):
         x = datagen.typed_keys(n, seed=47, dtype=np.float64).view(np.uint64)
         keys = np.where(x >> np.uint64(63) == 1, ~x, x | np.uint64(1 << 63))
     vals = datagen.index_values(n)
-    check_case(keys, vals, P, 0, ws=ws)
+    check_case(keys, vals, P, 0, ws=ws, rtile=rtile)
 
 
 def _sized_groups_block(rng, n_target, sizes, seed, low_bits=40):
@@ -184,8 +186,9 @@ def _sized_groups_block(rng, n_target, sizes, seed, low_bits=40):
     return keys[rng.permutation(len(keys))]
 
 
+@pytest.mark.parametrize("rtile", [0, 4096])
 @pytest.mark.parametrize("P", [1, 2])
-def test_group_sizes_at_the_thresholds(ws, P):
+def test_group_sizes_at_the_thresholds(ws, P, rtile):
     """Groups of every size class of the 64-bit fix-up at once, ranked in
     place (<= 64 keys), sorted by the mid-size kernel (65..512) or left for
     the eight-pass sort (> 512 different keys), straddling tiles and blocks."""
@@ -195,21 +198,21 @@ def test_group_sizes_at_the_thresholds(ws, P):
     # equal block sizes, so that block i is exactly the i-th part
     m = min(len(b) for b in blocks)
     keys = np.concatenate([b[:m] for b in blocks])
-    check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws)
+    check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws, rtile=rtile)
     # the same groups but no group above 512 keys: no block falls back
     sizes = [1, 64, 65, 100, 300, 512]
     blocks = [_sized_groups_block(rng, 300_000, sizes, 5000 * (b + 1)) for b in range(P)]
     m = min(len(b) for b in blocks)
     keys = np.concatenate([b[:m] for b in blocks])
-    check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws)
-    check_case(keys, None, P, 0, ws=ws)
+    check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws, rtile=rtile)
+    check_case(keys, None, P, 0, ws=ws, rtile=rtile)
     # groups whose keys differ only in their low 32 bits (long runs after the
     # first pass of the group sort) or only in their low 8 bits (many equal keys)
     for low_bits in (32, 8):
         blocks = [_sized_groups_block(rng, 200_000, sizes, 9000 * (b + 1), low_bits) for b in range(P)]
         m = min(len(b) for b in blocks)
         keys = np.concatenate([b[:m] for b in blocks])
-        check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws)
+        check_case(keys, datagen.index_values(len(keys)), P, 0, ws=ws, rtile=rtile)
 
 
 def test_batch_with_group_paths(ws):
@@ -246,3 +249,35 @@ def test_local_sort_paths_agree(ws, monkeypatch):
     monkeypatch.setenv("LBSORT_LOCAL_SORT", "lsd")
     b = check_case(keys, vals, 16, 0, ws=ws)[0]
     assert np.array_equal(ka, to_host(b.keys)) and np.array_equal(va, to_host(b.vals))
+
+
+@pytest.mark.parametrize("rtile", [4096, 8192])
+def test_radix_tile_settings(ws, rtile):
+    """Both radix tiles on the main shapes: u64 pairs at P = 64, u32 pairs,
+    blocks just above one and two tiles, the duplicate-heavy input, and the
+    two local-sort paths of 64-bit keys giving the same bytes."""
+    n = 3_000_017
+    check_case(datagen.uniform_keys(n, seed=2), datagen.index_values(n), 64, 512, ws=ws, rtile=rtile)
+    n = 1_234_567
+    check_case(datagen.uniform_keys(n, seed=5, dtype=np.uint32), datagen.index_values(n), 8, 0, ws=ws, rtile=rtile)
+    check_case(datagen.normal_u32(n, seed=6), None, 13, 0, ws=ws, rtile=rtile)
+    for n, P in ((4097, 1), (8191, 1), (8193, 1), (12_289, 3), (3 * 8192 + 5, 3), (50_000, 8)):
+        check_case(datagen.uniform_keys(n, seed=n + P), datagen.index_values(n), P, 4, ws=ws, rtile=rtile)
+    n = 2_000_003
+    keys = datagen.duplicate_heavy_keys(n, seed=3)
+    check_case(keys, datagen.index_values(n), 64, 512, ws=ws, rtile=rtile)
+
+
+def test_radix_tiles_agree_on_every_local_sort_path(ws, monkeypatch):
+    """Radix tiles of 4096 and 8192 keys, fix-up path and all eight passes:
+    the same bytes."""
+    keys = datagen.uniform_keys(1 << 21, seed=45)
+    vals = datagen.index_values(1 << 21)
+    ref = run_gpu(keys, vals, 16, 0, ws=ws)
+    ka, va = to_host(ref.keys).copy(), to_host(ref.vals).copy()
+    for lsd in (False, True):
+        if lsd:
+            monkeypatch.setenv("LBSORT_LOCAL_SORT", "lsd")
+        for rtile in (4096, 8192):
+            r = run_gpu(keys, vals, 16, 0, ws=ws, rtile=rtile)
+            assert np.array_equal(ka, to_host(r.keys)) and np.array_equal(va, to_host(r.vals)), (lsd, rtile)

@@ -462,3 +462,25 @@ def test_partition_plan_default_budget():
         for mode in (O.INV_COUNT, O.INV_PAPER):
             plan = _plan_vs_sample_sort(keys, P, 0, mode)
             assert all(len(x) == want for x in plan["samples"])
+
+
+def test_parallel_driver_equals_oracle():
+    """The process-parallel driver (steps 1 and 6 over a pool) gives exactly
+    the oracle's result."""
+    import multiprocessing as mp
+    from oracle.parallel import sample_sort_parallel
+    rng = np.random.default_rng(37)
+    with mp.get_context("spawn").Pool(2) as pool:
+        for trial in range(12):
+            n = int(rng.integers(0, 3000))
+            P = int(rng.integers(1, 12))
+            keys = rand_keys(rng, n, ALPHA if trial % 2 else None)
+            vals = np.arange(n, dtype=np.uint32) if trial % 3 else None
+            for mode in (O.INV_COUNT, O.INV_PAPER):
+                a = O.sample_sort(keys, vals, P, 0, mode)
+                b = sample_sort_parallel(keys, vals, P, 0, mode, pool=pool)
+                assert a.keys.tolist() == b.keys.tolist()
+                if vals is not None:
+                    assert a.vals.tolist() == b.vals.tolist()
+                assert a.part_offsets.tolist() == b.part_offsets.tolist()
+                assert a.cuts.tolist() == b.cuts.tolist() and a.splitters.tolist() == b.splitters.tolist()
