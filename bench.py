@@ -369,7 +369,7 @@ def run_batch(args, steps, warmup, tune=True, check=True):
 
 
 def bench_batch(args):
-    b = run_batch(args, args.steps, args.warmup)
+    b = run_batch(args, args.steps, args.warmup, tune=not args.no_tune)
     line = {"metric": "batched sort: GKeys/s (u32 keys + u32 values), one graph launch vs a per-instance loop",
             "value": b.pop("value"), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": b.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -590,9 +590,11 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
-def measure_sort(w, args, steps, warmup, profile=True):
+def measure_sort(w, args, steps, warmup, profile=True, tune=False):
     """Time one sort workload: `steps` steps without instrumentation (the
-    figure), then, with profile, `steps` more with per-launch events."""
+    figure), then, with profile, `steps` more with per-launch events.  With
+    tune, the autotuner first picks the radix tile, handler schedule, fan-in
+    and merge tile on this very input (the settings used are reported)."""
     import numpy as np
     import torch
     from paper_1611_00463_amd import lbsort as L
@@ -604,6 +606,13 @@ def measure_sort(w, args, steps, warmup, profile=True):
     has_v = bool(w["vals"])
     vout = torch.empty(w["n"], dtype=torch.uint32, device=dev) if has_v else None
     ws = L.Workspace(dev)
+    vt = (L.VAL_U32 if vals is not None else L.VAL_INDEX) if has_v else L.NOVAL
+    tuned = None
+    if tune and not (args.fanin or args.merge_tile):
+        print(f"[bench] autotuning {w['tag']}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        tuned = L.autotune(L.key_code(keys.dtype), vt, w["P"], keys=keys, vals=vals)
+        tuned["tuning_s"] = round(time.perf_counter() - t0, 2)
 
     def step():
         if not has_v:
@@ -642,10 +651,10 @@ def measure_sort(w, args, steps, warmup, profile=True):
     counts = r.part_counts.cpu().numpy()[0].astype(np.float64)
     imb = {"max_over_mean": round(float(counts.max() / counts.mean()), 6), "min": int(counts.min()),
            "max": int(counts.max()), "P": w["P"]}
-    used = L.resolve_params(L.key_code(keys.dtype), (L.VAL_U32 if vals is not None else L.VAL_INDEX) if has_v
-                            else L.NOVAL, w["P"], w["n"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile)
+    used = L.resolve_params(L.key_code(keys.dtype), vt, w["P"], w["n"], s=w["s"], fanin=args.fanin,
+                            merge_tile=args.merge_tile)
     out = dict(ms=ms, value=w["n"] / (ms / 1e3) / 1e9, prof=prof, ms_prof=ms_prof, imbalance=imb, settings=used,
-               kb=keys.element_size(), vb=4 if has_v else 0, dtype=KEY_NAMES[str(keys.dtype)])
+               autotuned=tuned, kb=keys.element_size(), vb=4 if has_v else 0, dtype=KEY_NAMES[str(keys.dtype)])
     del keys, vals, kout, vout, ws, r
     torch.cuda.empty_cache()
     return out
@@ -685,6 +694,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="pairs", choices=sorted(WORKLOADS) + ["batch", "serve", "balance", "search"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--no-tune", action="store_true", help="run with the default settings, no autotuning")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: leave out the duplicate-heavy and batched objects")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys of the all-cores oracle sample")
@@ -730,7 +740,7 @@ def main():
         print("[bench] timing the CPU oracle on samples", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, min(args.cpu_sample, w["n"]), min(args.cpu_sample_one, w["n"]))
     torch.cuda.set_device(torch.device("cuda:0"))
-    m = measure_sort(w, args, args.steps, args.warmup)
+    m = measure_sort(w, args, args.steps, args.warmup, tune=not args.no_tune)
     roof, pipe, kernels = summarize_sort(w, m, args.steps)
     line = {
         "metric": METRIC, "value": round(m["value"], 4), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
@@ -738,8 +748,9 @@ def main():
         "vs_baseline": None, "dtype": m["dtype"], "data": "synthetic",
         "config": {"workload": w["desc"], "n": w["n"], "P": w["P"], "s": w["s"], "key": m["dtype"],
                    "value": {True: "u32", "index": "u32 index (generated)", False: None}[w["vals"]],
-                   "investigator": "COUNT", "fanin": m["settings"]["fanin"],
-                   "merge_tile": m["settings"]["merge_tile"], "radix_tile": m["settings"]["radix_tile"]},
+                   "investigator": "COUNT", "handler": {1: "passes", 2: "one pass"}[m["settings"]["handler"]],
+                   "fanin": m["settings"]["fanin"], "merge_tile": m["settings"]["merge_tile"],
+                   "radix_tile": m["settings"]["radix_tile"], "autotuned": m["autotuned"]},
         "imbalance": m["imbalance"],
         "roofline": roof,
         "pipeline": pipe,
@@ -748,13 +759,14 @@ def main():
     }
     if args.workload == "pairs" and not args.no_extras:
         wd = WORKLOADS["dups"]
-        md = measure_sort(wd, args, max(3, args.steps // 2), 1)
+        md = measure_sort(wd, args, max(3, args.steps // 2), 1, tune=not args.no_tune)
         rd, pd, _ = summarize_sort(wd, md, max(3, args.steps // 2))
         line["dups"] = {"workload": wd["desc"], "value": round(md["value"], 4), "unit": "GKeys/s",
                         "ms_per_step": round(md["ms"], 4), "imbalance": md["imbalance"],
+                        "settings": md["settings"], "autotuned": md["autotuned"],
                         "roofline": {k: rd[k] for k in ("kernel", "achieved", "frac", "avg_launch_ms")},
                         "pipeline": {k: pd[k] for k in ("executed_bytes_per_key", "executed_frac", "model_frac")}}
-        line["batched"] = run_batch(args, max(3, args.steps // 2), 1)
+        line["batched"] = run_batch(args, max(3, args.steps // 2), 1, tune=not args.no_tune)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -97,12 +97,29 @@ typedef struct lbsort_params {
                             taken as the largest multiple of P not above b (b if b < P,
                             at least 1)                                                     */
   uint32_t investigator; /* LBSORT_INV_*                                                     */
-  uint32_t fanin;        /* handler merge fan-in F per pass: 0 = tuned, else 2, 4, 8 or 16   */
-  uint32_t merge_tile;   /* elements per merge tile: 0 = tuned, else 1024, 2048 or 4096     */
+  uint32_t fanin;        /* handler merge fan-in F per pass: 0 = tuned, else 2, 4, 8 or 16
+                            (LBSORT_HANDLER_PASSES); with LBSORT_HANDLER_ONE_PASS 0 or the
+                            power of two reaching P (up to 64)                              */
+  uint32_t merge_tile;   /* elements per merge tile: 0 = tuned, else 1024, 2048 or 4096
+                            (LBSORT_HANDLER_ONE_PASS: 2048 or 4096, the tile's capacity)    */
   uint32_t radix_tile;   /* keys per radix tile of the local sort: 0 = tuned, else 4096 or
                             8192 (digits are 8 bits wide in every case)                     */
+  uint32_t handler;      /* step 6: 0 = tuned, LBSORT_HANDLER_PASSES or
+                            LBSORT_HANDLER_ONE_PASS                                         */
   uint32_t reserved;     /* must be 0                                                        */
 } lbsort_params;
+
+/* Handler (step 6, Section IV.A, Fig. 2) schedules.  Both merge each
+ * partition's P runs stably (ties to the lower block) and give the same bytes.
+ *   PASSES:   ceil(log_F P) passes of F-way merges; every tile of a pass holds
+ *             exactly merge_tile outputs, its boundary found by an exact
+ *             multi-sequence selection.
+ *   ONE_PASS: one pass of a P-way merge (P <= 64, total_n <= 2^32); tile
+ *             boundaries are regular samples of the runs (every 16th element
+ *             of each run, merged by the PASSES schedule at 1/16 of the size),
+ *             which bounds every tile by merge_tile without selection rounds. */
+#define LBSORT_HANDLER_PASSES 1
+#define LBSORT_HANDLER_ONE_PASS 2
 
 /* Partition outputs (device arrays).  For a batch every array is stacked per
  * instance: instance b's part_offsets are at part_offsets[b*(P+1)], etc. */
@@ -146,8 +163,9 @@ int lbsort_sort_pairs(int key_type, int val_type, const void *keys_in, const voi
  *
  * Limit: a problem whose workspace (as lbsort_sort_pairs would size it)
  * exceeds LBSORT_NOALLOC_SCRATCH_BYTES returns LBSORT_ERR_UNSUPPORTED before
- * anything is enqueued; that is about 5 million 64-bit keys with values, or
- * 8 million 32-bit keys with values.
+ * anything is enqueued; that is about 5.3 million 64-bit keys with values
+ * (4.6 million with LBSORT_HANDLER_ONE_PASS at P = 64), or 7.9 million
+ * 32-bit keys with values.
  *
  * All calls on one device share that device's array and each call starts
  * by clearing what must start at zero: calls that overlap on one device
@@ -236,9 +254,11 @@ const char *lbsort_last_error(void);
  * the current device and records the fastest in the tuning cache, keyed by
  * the device architecture, the key width, values or not, the instance size
  * (total_n / B, to a power of two), batched or not, and P.  Searched: the
- * radix tile (4096, 8192) and the handler fan-in F (2 .. 16, at most the
- * power of two above P) with the default merge tile, then the merge tile
- * (1024, 2048, 4096) with the best of those.  Every candidate must produce
+ * radix tile (4096, 8192) and the handler schedule (LBSORT_HANDLER_PASSES
+ * with each fan-in F = 2 .. 16 up to the power of two above P, and
+ * LBSORT_HANDLER_ONE_PASS where it applies) with the default merge tile, then
+ * the merge tile (1024, 2048, 4096; 2048 or 4096 for one pass) with the best
+ * of those.  Every candidate must produce
  * the same bytes (keys, values, part_offsets) as the first, else
  * LBSORT_ERR_DEVICE.  The radix digit is 8 bits wide in every case.
  *
@@ -262,8 +282,9 @@ int lbsort_load_tuning(const char *cache_path);
 /*
  * The settings a sort call with these arguments would run with on the
  * current device (host only, nothing enqueued): P, s (the default budget
- * resolved), investigator, and fanin / merge_tile / radix_tile as given,
- * else from the tuning cache, else the defaults.  out (host) receives them.
+ * resolved), investigator, and fanin / merge_tile / radix_tile / handler as
+ * given, else from the tuning cache, else the defaults.  out (host) receives
+ * them.
  */
 int lbsort_resolve_params(int key_type, int val_type, uint32_t B, uint64_t total_n,
                           const lbsort_params *params, lbsort_params *out);

@@ -34,6 +34,9 @@ void launch_split(const Plan& p, const K* sorted, u64 max_samples, const void* o
                   void* out_send, void* out_cuts, void* out_split, hipStream_t s);
 template <typename K, bool HASV>
 void launch_merge_level(const Plan& p, u32 level, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s);
+template <typename K, bool HASV>
+void launch_handler_sampled(const Plan& p, const Plan& ps, const SampPlan& sp, u64 max_tiles, const K* sorted,
+                            const u32* sortedv, K* dst, u32* dstv, hipStream_t s);
 template <typename K>
 void launch_key_out(K* a, u64 n, u64 top, u64 fm, hipStream_t s);
 template <typename K>
@@ -117,11 +120,21 @@ struct Shape {
   u32 ng0;          // merge groups of pass 0 (the largest pass)
   u64 mtiles;       // merge tiles of one pass, worst case
   bool local_only;  // step 1 only
+  u32 handler;      // LBSORT_HANDLER_PASSES or LBSORT_HANDLER_ONE_PASS
+  // one-pass handler: the sample problem (sample slots with gaps between
+  // instances, its multi-pass merge: fan-in, tile, passes, groups, tiles)
+  u64 s_max;
+  u32 s_F, s_TM, s_L, s_ng0;
+  u64 s_mtiles;
+  u32 q;            // sorted samples per merge tile
 };
 
 struct Layout {
   u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, tdesc, gflags, gflags2, midlist, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
       splitters, mtile, rec_start, rec_end, rec_out, rec_n, slot_grp, grp_run, grp_out, tmpk, tmpv, seg, total;
+  // one-pass handler
+  u64 sseg, sbs, scuts, sDm, gsbase, ntile, skeys[2], svals[2], s_mtile, s_rec_start, s_rec_end, s_rec_out, s_rec_n,
+      s_slot_grp, s_grp_run, s_grp_out;
 };
 
 // Entries of the mid-size group list: groups of more than GF_HALO keys in the
@@ -174,6 +187,26 @@ static Layout make_layout(const Shape& sh) {
   l.tmpk = take(need_tmp ? sh.total_n * K : 0);
   l.tmpv = take(need_tmp && sh.val_type ? sh.total_n * 4 : 0);
   l.seg = take(16);
+  const bool one = sh.handler == LBSORT_HANDLER_ONE_PASS && sh.L > 0;
+  const u64 sm = one ? sh.s_max : 0;
+  l.sseg = take(one ? (B + 1) * 8 : 0);
+  l.sbs = take(one ? (NB + 1) * 8 : 0);
+  l.scuts = take(one ? B * P * (P + 1) * 8 : 0);
+  l.sDm = take(one ? B * (P + 1) * P * 8 : 0);
+  l.gsbase = take(one ? NB * 8 : 0);
+  l.ntile = take(one ? NB * 4 : 0);
+  for (int x = 0; x < 2; ++x) {
+    l.skeys[x] = take(sm * K);
+    l.svals[x] = take(sm * 4);
+  }
+  l.s_mtile = take(one ? ((u64)sh.s_ng0 + 1) * 4 : 0);
+  l.s_rec_start = take(one ? sh.s_mtiles * sh.s_F * 8 : 0);
+  l.s_rec_end = take(one ? sh.s_mtiles * sh.s_F * 8 : 0);
+  l.s_rec_out = take(one ? sh.s_mtiles * 8 : 0);
+  l.s_rec_n = take(one ? sh.s_mtiles * 4 : 0);
+  l.s_slot_grp = take(one ? (sh.s_mtiles + sh.s_ng0 + 1) * 4 : 0);
+  l.s_grp_run = take(one ? (u64)sh.s_ng0 * sh.s_F * 16 : 0);
+  l.s_grp_out = take(one ? (u64)sh.s_ng0 * 16 : 0);
   l.total = o;
   return l;
 }
@@ -187,12 +220,16 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
                 val_type);
   if (val_type == LBSORT_VAL_INDEX && B == 1 && total_n > (1ull << 32))
     return fail(LBSORT_ERR_UNSUPPORTED, "LBSORT_VAL_INDEX needs n <= 2^32 (32-bit positions)");
-  lbsort_params d = {1, 0, LBSORT_INV_COUNT, 0, 0, 0, 0};
+  lbsort_params d = {1, 0, LBSORT_INV_COUNT, 0, 0, 0, 0, 0};
   const lbsort_params& p = prm ? *prm : d;
   if (p.P < 1 || p.P > LBSORT_MAX_P) return fail(LBSORT_ERR_INVALID_ARG, "P must be in [1, %d] (got %u)", LBSORT_MAX_P, p.P);
   if (p.investigator > 2) return fail(LBSORT_ERR_INVALID_ARG, "unknown investigator mode %u", p.investigator);
   if (p.s > LBSORT_MAX_SAMPLES) return fail(LBSORT_ERR_INVALID_ARG, "s must be <= %u (got %u)", LBSORT_MAX_SAMPLES, p.s);
-  if (p.fanin != 0 && p.fanin != 2 && p.fanin != 4 && p.fanin != 8 && p.fanin != 16)
+  if (p.handler > LBSORT_HANDLER_ONE_PASS)
+    return fail(LBSORT_ERR_INVALID_ARG, "handler must be 0, LBSORT_HANDLER_PASSES or LBSORT_HANDLER_ONE_PASS (got %u)",
+                p.handler);
+  if (p.handler != LBSORT_HANDLER_ONE_PASS && p.fanin != 0 && p.fanin != 2 && p.fanin != 4 && p.fanin != 8 &&
+      p.fanin != 16)
     return fail(LBSORT_ERR_INVALID_ARG, "fanin must be 0, 2, 4, 8 or 16 (got %u)", p.fanin);
   if (p.merge_tile != 0 && p.merge_tile != 1024 && p.merge_tile != 2048 && p.merge_tile != 4096)
     return fail(LBSORT_ERR_INVALID_ARG, "merge_tile must be 0, 1024, 2048 or 4096 (got %u)", p.merge_tile);
@@ -219,14 +256,45 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   // merge fan-in and tile: explicit, else tuned, else defaults
   // tuned settings depend on the widths only
   Tuned tu = tuning_lookup(kb, val_type != LBSORT_NOVAL, total_n / B, B, p.P);
-  u32 F = p.fanin ? p.fanin : tu.fanin;
-  if (!F) {
-    F = 2;
-    while (F < p.P && F < 16) F *= 2;
-    if (p.P > 16) F = 8;
+  // step 6: one pass with sampled tiles (P <= 64, positions in 32 bits), or
+  // F-way passes with exact tiles
+  const bool one_ok = p.P >= 2 && p.P <= 64 && total_n <= (1ull << 32);
+  u32 handler = p.handler;
+  // an explicit fan-in of the passes, or a tile only they take, implies them
+  if (!handler && ((p.fanin && p.fanin <= 16) || p.merge_tile == 1024)) handler = LBSORT_HANDLER_PASSES;
+  if (!handler) handler = tu.handler;
+  // untuned: the exact passes (the one-pass schedule wins on inputs with
+  // heavy duplicates, where exact selection needs many rounds; the tuner
+  // picks it there)
+  if (!handler) handler = LBSORT_HANDLER_PASSES;
+  if (handler == LBSORT_HANDLER_ONE_PASS && !one_ok) {
+    if (p.handler == LBSORT_HANDLER_ONE_PASS && p.P >= 2)
+      return fail(LBSORT_ERR_UNSUPPORTED, "the one-pass handler needs P <= 64 and total_n <= 2^32");
+    handler = LBSORT_HANDLER_PASSES;
+  }
+  if (p.P < 2) handler = LBSORT_HANDLER_PASSES;
+  sh.handler = handler;
+  u32 pow2P = 2;
+  while (pow2P < p.P) pow2P *= 2;
+  u32 F;
+  if (handler == LBSORT_HANDLER_ONE_PASS) {
+    if (p.fanin && p.fanin != pow2P)
+      return fail(LBSORT_ERR_INVALID_ARG, "with the one-pass handler fanin must be 0 or %u for P = %u (got %u)", pow2P,
+                  p.P, p.fanin);
+    F = pow2P;
+    if (p.merge_tile == 1024)
+      return fail(LBSORT_ERR_INVALID_ARG, "the one-pass handler's merge_tile must be 2048 or 4096");
+    sh.TM = p.merge_tile ? p.merge_tile : (tu.merge_tile >= 2048 && tu.handler == handler ? tu.merge_tile : 4096u);
+    if (sh.TM / SAMP_STRIDE <= p.P) sh.TM = 4096;
+  } else {
+    F = p.fanin ? p.fanin : (tu.handler == handler ? tu.fanin : 0);
+    if (!F) {
+      F = pow2P < 16 ? pow2P : 16;
+      if (p.P > 16) F = 8;
+    }
+    sh.TM = p.merge_tile ? p.merge_tile : (tu.merge_tile && tu.handler == handler ? tu.merge_tile : 2048u);
   }
   sh.F = F;
-  sh.TM = p.merge_tile ? p.merge_tile : (tu.merge_tile ? tu.merge_tile : 2048u);
   sh.rtile = p.radix_tile ? p.radix_tile : (tu.radix_tile ? tu.radix_tile : RTILE_LARGE);
   u32 L = 0;
   for (u64 span = 1; span < p.P; span *= F) ++L;
@@ -258,6 +326,23 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   const u64 Q0 = (p.P + F - 1) / F;
   sh.ng0 = (u32)(NB * Q0);
   sh.mtiles = sh.L ? total_n / sh.TM + sh.ng0 + 1 : 0;
+  sh.s_max = 0;
+  sh.s_F = sh.s_TM = sh.s_L = sh.s_ng0 = sh.q = 0;
+  sh.s_mtiles = 0;
+  if (sh.handler == LBSORT_HANDLER_ONE_PASS && sh.L > 0) {
+    // every run (B P^2 of them) adds at most one sample above len / m
+    const u64 PP = (u64)p.P * p.P;
+    sh.s_max = total_n / SAMP_STRIDE + (u64)B * (PP + 1) + 1;
+    sh.q = sh.TM / SAMP_STRIDE - p.P;
+    sh.mtiles = (total_n / SAMP_STRIDE + B * PP) / sh.q + NB + 1;
+    sh.s_F = pow2P < 16 ? pow2P : 16;
+    if (p.P > 16) sh.s_F = 8;
+    sh.s_TM = 2048;
+    sh.s_L = 0;
+    for (u64 span = 1; span < p.P; span *= sh.s_F) ++sh.s_L;
+    sh.s_ng0 = (u32)(NB * ((p.P + sh.s_F - 1) / sh.s_F));
+    sh.s_mtiles = sh.s_max / sh.s_TM + sh.s_ng0 + 1;
+  }
   return LBSORT_OK;
 }
 
@@ -405,9 +490,47 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
     const K* sorted = dk(sh.D - 1);
     launch_split<K>(py, sorted, sh.max_samples, parts->part_offsets, parts->part_counts, parts->send_counts,
                     parts->cuts, parts->splitters, st);
-    for (u32 l = 0; l < sh.L; ++l)
-      launch_merge_level<K, HASV>(l + 1 == sh.L ? py : p, l, dk(sh.D - 1 + l), dv(sh.D - 1 + l), dk(sh.D + l),
-                                  dv(sh.D + l), st);
+    if (sh.handler == LBSORT_HANDLER_ONE_PASS && sh.L == 1) {
+      // the sample problem: its own layout of blocks, cuts and range table,
+      // and its own merge records (the main tile records are written later)
+      SampPlan sp;
+      sp.sseg = (u64*)(ws + lay.sseg);
+      sp.sbs = (u64*)(ws + lay.sbs);
+      sp.scuts = (u64*)(ws + lay.scuts);
+      sp.sDm = (u64*)(ws + lay.sDm);
+      sp.gsbase = (u64*)(ws + lay.gsbase);
+      sp.ntile = (u32*)(ws + lay.ntile);
+      for (int x = 0; x < 2; ++x) {
+        sp.skeys[x] = ws + lay.skeys[x];
+        sp.svals[x] = (u32*)(ws + lay.svals[x]);
+      }
+      sp.m = SAMP_STRIDE;
+      sp.q = sh.q;
+      Plan ps = p;
+      ps.seg = sp.sseg;
+      ps.blk_start = sp.sbs;
+      ps.cuts = sp.scuts;
+      ps.Dm = sp.sDm;
+      ps.F = sh.s_F;
+      ps.TM = sh.s_TM;
+      ps.L = sh.s_L;
+      ps.total_n = sh.s_max;
+      ps.mtile = (u32*)(ws + lay.s_mtile);
+      ps.rec_start = (u64*)(ws + lay.s_rec_start);
+      ps.rec_end = (u64*)(ws + lay.s_rec_end);
+      ps.rec_out = (u64*)(ws + lay.s_rec_out);
+      ps.rec_n = (u32*)(ws + lay.s_rec_n);
+      ps.slot_grp = (u32*)(ws + lay.s_slot_grp);
+      ps.grp_run = (u64*)(ws + lay.s_grp_run);
+      ps.grp_out = (u64*)(ws + lay.s_grp_out);
+      ps.ng_max = sh.s_ng0;
+      ps.mtiles_max = (u32)sh.s_mtiles;
+      launch_handler_sampled<K, HASV>(py, ps, sp, sh.mtiles, sorted, dv(sh.D - 1), dk(sh.D), dv(sh.D), st);
+    } else {
+      for (u32 l = 0; l < sh.L; ++l)
+        launch_merge_level<K, HASV>(l + 1 == sh.L ? py : p, l, dk(sh.D - 1 + l), dv(sh.D - 1 + l), dk(sh.D + l),
+                                    dv(sh.D + l), st);
+    }
   }
   // without a merge pass the local sort wrote keys_out: map it back in place
   if (sh.L == 0 && (top | fm) != 0) launch_key_out<K>(kout, sh.total_n, top, fm, st);
@@ -551,7 +674,7 @@ int lbsort_resolve_params(int key_type, int val_type, uint32_t B, uint64_t total
   Shape sh;
   int rc = make_shape(key_type, val_type, B, total_n, params, false, sh);
   if (rc) return rc;
-  lbsort_params r = {sh.P, sh.s, sh.inv, sh.F, sh.TM, sh.rtile, 0};
+  lbsort_params r = {sh.P, sh.s, sh.inv, sh.F, sh.TM, sh.rtile, sh.handler, 0};
   *out = r;
   return LBSORT_OK;
 }

@@ -234,11 +234,11 @@ __device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* 
   }
 }
 
-template <typename K, bool HASV, int F, int TM>
-__global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restrict__ src,
-                                               const u32* __restrict__ srcv, K* __restrict__ dst,
-                                               u32* __restrict__ dstv) {
-  constexpr int NT = 256, IT = TM / NT, TP = TM + TM / 8 + 8;  // 8 slack slots past pad8(TM - 1)
+template <typename K, bool HASV, int F, int TM, int NT = 256>
+__global__ __launch_bounds__(NT) void k_merge(Plan p, Level L, const K* __restrict__ src,
+                                              const u32* __restrict__ srcv, K* __restrict__ dst,
+                                              u32* __restrict__ dstv) {
+  constexpr int IT = TM / NT, TP = TM + TM / 8 + 8;  // 8 slack slots past pad8(TM - 1)
   __shared__ K s_k[TP];
   __shared__ uint16_t s_i[HASV ? TP : 1];
   __shared__ u32 s_v[HASV ? TM : 1];
@@ -264,6 +264,9 @@ __global__ __launch_bounds__(256) void k_merge(Plan p, Level L, const K* __restr
       acc += s_so[r];
       s_so[r] = acc < cap ? acc : cap;
     }
+    // a tile can never hold more than its records allow; if it did, the
+    // clamp above would drop elements: report it
+    if (acc > cap) set_error(p.counters, E_SELECT);
   }
   __syncthreads();
   const u32 n = s_so[F];
@@ -385,6 +388,60 @@ void launch_merge_level(const Plan& p, u32 level, const K* src, const u32* srcv,
     default: run_level_tm<K, HASV, 8>(p, L, src, srcv, dst, dstv, max_tiles, s); break;
   }
 }
+
+// The one-pass handler's merge: tiles and their records come from the sampled
+// tile bounds (k_samp_bounds); F = 32 or 64 runs per tile, TM = 2048 or 4096
+// elements, eight per thread.
+template <typename K, bool HASV>
+void launch_merge_sampled(const Plan& p, u32 NG, u64 max_tiles, const K* src, const u32* srcv, K* dst, u32* dstv,
+                          hipStream_t s) {
+  Level L;
+  L.level = 0;
+  L.RS = 1;
+  L.GS = p.F;
+  L.Q = 1;
+  L.NG = NG;
+  if (max_tiles == 0) return;
+  const int pe_ = prof_begin(s);
+  const dim3 grid((u32)max_tiles);
+  if (p.F == 32) {
+    if (p.TM == 4096)
+      hipLaunchKernelGGL((k_merge<K, HASV, 32, 4096, 512>), grid, dim3(512), 0, s, p, L, src, srcv, dst, dstv);
+    else
+      hipLaunchKernelGGL((k_merge<K, HASV, 32, 2048, 256>), grid, dim3(256), 0, s, p, L, src, srcv, dst, dstv);
+  } else if (p.F == 64) {
+    if (p.TM == 4096)
+      hipLaunchKernelGGL((k_merge<K, HASV, 64, 4096, 512>), grid, dim3(512), 0, s, p, L, src, srcv, dst, dstv);
+    else
+      hipLaunchKernelGGL((k_merge<K, HASV, 64, 2048, 256>), grid, dim3(256), 0, s, p, L, src, srcv, dst, dstv);
+  } else if (p.F == 16) {
+    if (p.TM == 4096)
+      hipLaunchKernelGGL((k_merge<K, HASV, 16, 4096, 512>), grid, dim3(512), 0, s, p, L, src, srcv, dst, dstv);
+    else
+      hipLaunchKernelGGL((k_merge<K, HASV, 16, 2048, 256>), grid, dim3(256), 0, s, p, L, src, srcv, dst, dstv);
+  } else if (p.F == 8) {
+    if (p.TM == 4096)
+      hipLaunchKernelGGL((k_merge<K, HASV, 8, 4096, 512>), grid, dim3(512), 0, s, p, L, src, srcv, dst, dstv);
+    else
+      hipLaunchKernelGGL((k_merge<K, HASV, 8, 2048, 256>), grid, dim3(256), 0, s, p, L, src, srcv, dst, dstv);
+  } else if (p.F == 4) {
+    if (p.TM == 4096)
+      hipLaunchKernelGGL((k_merge<K, HASV, 4, 4096, 512>), grid, dim3(512), 0, s, p, L, src, srcv, dst, dstv);
+    else
+      hipLaunchKernelGGL((k_merge<K, HASV, 4, 2048, 256>), grid, dim3(256), 0, s, p, L, src, srcv, dst, dstv);
+  } else {
+    if (p.TM == 4096)
+      hipLaunchKernelGGL((k_merge<K, HASV, 2, 4096, 512>), grid, dim3(512), 0, s, p, L, src, srcv, dst, dstv);
+    else
+      hipLaunchKernelGGL((k_merge<K, HASV, 2, 2048, 256>), grid, dim3(256), 0, s, p, L, src, srcv, dst, dstv);
+  }
+  prof_end(pe_, "merge", s);
+}
+
+template void launch_merge_sampled<u32, false>(const Plan&, u32, u64, const u32*, const u32*, u32*, u32*, hipStream_t);
+template void launch_merge_sampled<u32, true>(const Plan&, u32, u64, const u32*, const u32*, u32*, u32*, hipStream_t);
+template void launch_merge_sampled<u64, false>(const Plan&, u32, u64, const u64*, const u32*, u64*, u32*, hipStream_t);
+template void launch_merge_sampled<u64, true>(const Plan&, u32, u64, const u64*, const u32*, u64*, u32*, hipStream_t);
 
 template void launch_merge_level<u32, false>(const Plan&, u32, const u32*, const u32*, u32*, u32*, hipStream_t);
 template void launch_merge_level<u32, true>(const Plan&, u32, const u32*, const u32*, u32*, u32*, hipStream_t);

@@ -137,6 +137,24 @@ struct Plan {
   u32* pass_tmpv;
 };
 
+// The one-pass handler's sample problem (kernels_sampled.hip): the samples of
+// every run, laid out like the main problem's blocks, cut matrix and range
+// table, plus per partition (group g = instance * P + k) the start of its
+// sorted samples and its number of merge tiles.
+struct SampPlan {
+  u64* sseg;      // [B+1]  sample instance starts
+  u64* sbs;       // [NB+1] sample block starts
+  u64* scuts;     // [B][P][P+1] sample cuts per block
+  u64* sDm;       // [B][P+1][P] sample receive offsets (row P: partition ends)
+  u64* gsbase;    // [NB] first sorted sample of each partition
+  u32* ntile;     // [NB] merge tiles of each partition
+  void* skeys[2]; // sample keys, gathered (0) and merged (ping-pong)
+  u32* svals[2];  // their positions in the sorted blocks
+  u32 m;          // sample stride inside a run
+  u32 q;          // sorted samples per merge tile
+};
+constexpr u32 SAMP_STRIDE = 16;
+
 // ----------------------------------------------------------------- helpers
 template <typename K>
 struct KeyT;

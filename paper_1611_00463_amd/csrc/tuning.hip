@@ -1,5 +1,6 @@
-// Autotuner: picks the radix tile of the local sort, the handler's fan-in F
-// and its merge tile for one shape by timing the candidates on the device
+// Autotuner: picks the radix tile of the local sort, the handler's schedule
+// (F-way passes or one sampled pass), its fan-in F and its merge tile for one
+// shape by timing the candidates on the device
 // (on the caller's own data, or on synthetic uniform instances), checks that
 // every candidate produced the same bytes as the first, and keeps the winner
 // in an in-process table keyed by the device architecture, which can be
@@ -21,7 +22,7 @@ namespace lbs {
 
 struct Entry {
   std::string arch;  // e.g. "gfx950"
-  uint32_t key_bytes, values, size_log2, batched, P, fanin, merge_tile, radix_tile;
+  uint32_t key_bytes, values, size_log2, batched, P, fanin, merge_tile, radix_tile, handler;
   double ms;
 };
 
@@ -76,7 +77,7 @@ static int parse_file(const char* path, std::vector<Entry>& out) {
   while ((r = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, r);
   fclose(f);
   // One object per entry: {"arch": "..", "key_bytes": .., "values": .., "size_log2": .., "batched": ..,
-  // "P": .., "fanin": .., "merge_tile": .., "radix_tile": .., "ms": ..}
+  // "P": .., "fanin": .., "merge_tile": .., "radix_tile": .., "handler": .., "ms": ..}
   size_t pos = 0;
   while ((pos = s.find('{', pos + 1)) != std::string::npos) {
     size_t end = s.find('}', pos);
@@ -99,12 +100,13 @@ static int parse_file(const char* path, std::vector<Entry>& out) {
       return true;
     };
     std::string arch;
-    double kb, vt, sl, b, P, F, T, R, ms = 0;
+    double kb, vt, sl, b, P, F, T, R, H, ms = 0;
     if (str("arch", arch) && num("key_bytes", kb) && num("values", vt) && num("size_log2", sl) &&
-        num("batched", b) && num("P", P) && num("fanin", F) && num("merge_tile", T) && num("radix_tile", R)) {
+        num("batched", b) && num("P", P) && num("fanin", F) && num("merge_tile", T) && num("radix_tile", R) &&
+        num("handler", H)) {
       num("ms", ms);
       out.push_back(Entry{arch, (uint32_t)kb, (uint32_t)vt, (uint32_t)sl, (uint32_t)b, (uint32_t)P, (uint32_t)F,
-                          (uint32_t)T, (uint32_t)R, ms});
+                          (uint32_t)T, (uint32_t)R, (uint32_t)H, ms});
     }
     pos = end;
   }
@@ -119,9 +121,9 @@ static int write_file(const char* path) {
     const Entry& e = g_table[i];
     fprintf(f,
             "  {\"arch\": \"%s\", \"key_bytes\": %u, \"values\": %u, \"size_log2\": %u, \"batched\": %u, \"P\": %u, "
-            "\"fanin\": %u, \"merge_tile\": %u, \"radix_tile\": %u, \"ms\": %.4f}%s\n",
+            "\"fanin\": %u, \"merge_tile\": %u, \"radix_tile\": %u, \"handler\": %u, \"ms\": %.4f}%s\n",
             e.arch.c_str(), e.key_bytes, e.values, e.size_log2, e.batched, e.P, e.fanin, e.merge_tile, e.radix_tile,
-            e.ms, i + 1 < g_table.size() ? "," : "");
+            e.handler, e.ms, i + 1 < g_table.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -150,7 +152,7 @@ Tuned tuning_lookup(uint32_t key_bytes, bool values, uint64_t n, uint32_t B, uin
         for (auto& e : v) upsert(e);
     }
   }
-  Tuned t = {0, 0, 0};
+  Tuned t = {0, 0, 0, 0};
   if (arch.empty()) return t;
   const uint32_t sc = size_class(n);
   const uint32_t batched = B > 1 ? 1 : 0;
@@ -165,6 +167,7 @@ Tuned tuning_lookup(uint32_t key_bytes, bool values, uint64_t n, uint32_t B, uin
     t.fanin = best->fanin;
     t.merge_tile = best->merge_tile;
     t.radix_tile = best->radix_tile;
+    t.handler = best->handler;
   }
   return t;
 }
@@ -216,13 +219,21 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
   const std::string arch = current_arch();
   if (arch.empty()) return LBSORT_ERR_HIP;
   const bool hasv = val_type != LBSORT_NOVAL;
-  // candidates: radix tile and fan-in with the default merge tile first, then
-  // the merge tiles with the best of those
-  std::vector<uint32_t> fans;
+  // candidates: radix tile x handler schedule (each exact fan-in, and the
+  // one-pass schedule where it applies) with the default merge tile first,
+  // then the merge tiles with the best of those
+  struct Sched {
+    uint32_t handler, fanin;
+  };
+  std::vector<Sched> scheds;
   for (uint32_t F : {2u, 4u, 8u, 16u}) {
     if (F > 2 && F / 2 >= P) break;
-    fans.push_back(F);
+    scheds.push_back(Sched{LBSORT_HANDLER_PASSES, F});
   }
+  const bool one_ok = P >= 2 && P <= 64 && total_n <= (1ull << 32);
+  uint32_t pow2P = 2;
+  while (pow2P < P) pow2P *= 2;
+  if (one_ok) scheds.push_back(Sched{LBSORT_HANDLER_ONE_PASS, pow2P});
   const uint32_t rtiles[2] = {4096, 8192}, mtiles[3] = {1024, 2048, 4096};
   void *kin = nullptr, *kout = nullptr, *kref = nullptr, *ws = nullptr;
   uint32_t *vin = nullptr, *vout = nullptr, *vref = nullptr;
@@ -233,13 +244,13 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
   int rc = LBSORT_OK;
   size_t ws_need = 0;
   double best_ms = 1e30;
-  uint32_t best_f = 0, best_t = 0, best_r = 0;
+  uint32_t best_f = 0, best_t = 0, best_r = 0, best_h = 0;
   bool have_ref = false;
   lbsort_parts parts;
   memset(&parts, 0, sizeof parts);
   const uint64_t noffs = (uint64_t)B * (P + 1);
-  auto measure = [&](uint32_t R, uint32_t F, uint32_t T) -> int {
-    lbsort_params prm = {P, 0, LBSORT_INV_COUNT, F, T, R, 0};
+  auto measure = [&](uint32_t R, Sched h, uint32_t T) -> int {
+    lbsort_params prm = {P, 0, LBSORT_INV_COUNT, h.fanin, T, R, h.handler, 0};
     size_t wsb = ws_need;
     float times[5];
     for (int it = 0; it < 6; ++it) {
@@ -276,16 +287,18 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
     std::sort(times, times + 5);
     if (times[2] < best_ms) {
       best_ms = times[2];
-      best_f = F;
+      best_f = h.fanin;
       best_t = T;
       best_r = R;
+      best_h = h.handler;
     }
     return LBSORT_OK;
   };
   for (uint32_t R : rtiles)
-    for (uint32_t F : fans)
+    for (Sched h : scheds)
       for (uint32_t T : mtiles) {
-        lbsort_params prm = {P, 0, LBSORT_INV_COUNT, F, T, R, 0};
+        if (h.handler == LBSORT_HANDLER_ONE_PASS && T < 2048) continue;
+        lbsort_params prm = {P, 0, LBSORT_INV_COUNT, h.fanin, T, R, h.handler, 0};
         size_t need = 0;
         parts.part_offsets = (uint64_t*)1;  // the size query reads no pointer
         rc = lbsort_sort_batch(key_type, val_type, nullptr, nullptr, nullptr, nullptr, (const uint64_t*)1, B, total_n,
@@ -330,22 +343,24 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
   }
   parts.part_offsets = offs;
   for (uint32_t R : rtiles)
-    for (uint32_t F : fans)
-      if ((rc = measure(R, F, 2048)) != LBSORT_OK) goto done;
+    for (Sched h : scheds)
+      if ((rc = measure(R, h, h.handler == LBSORT_HANDLER_ONE_PASS ? 4096 : 2048)) != LBSORT_OK) goto done;
   {
-    const uint32_t R = best_r, F = best_f;
+    const uint32_t R = best_r, T0 = best_t;
+    const Sched h = {best_h, best_f};
     for (uint32_t T : mtiles)
-      if (T != 2048 && (rc = measure(R, F, T)) != LBSORT_OK) goto done;
+      if (T != T0 && !(h.handler == LBSORT_HANDLER_ONE_PASS && T < 2048) && (rc = measure(R, h, T)) != LBSORT_OK)
+        goto done;
   }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     upsert(Entry{arch, (uint32_t)kb, hasv ? 1u : 0u, size_class(total_n / B), B > 1 ? 1u : 0u, P, best_f, best_t,
-                 best_r, best_ms});
+                 best_r, best_h, best_ms});
     const char* path = (cache_path && *cache_path) ? cache_path : getenv("LBSORT_TUNE_CACHE");
     if (path && *path && write_file(path) != 0) rc = LBSORT_ERR_INVALID_ARG;
   }
   if (chosen) {
-    lbsort_params c = {P, 0, LBSORT_INV_COUNT, best_f, best_t, best_r, 0};
+    lbsort_params c = {P, 0, LBSORT_INV_COUNT, best_f, best_t, best_r, best_h, 0};
     *chosen = c;
   }
 done:

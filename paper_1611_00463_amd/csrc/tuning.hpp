@@ -1,4 +1,4 @@
-// Tuning cache: handler fan-in, merge tile and radix tile per shape and
+// Tuning cache: handler schedule, fan-in, merge tile and radix tile per shape and
 // device architecture, chosen by measurement (lbsort_autotune).
 #pragma once
 #include <stdint.h>
@@ -9,6 +9,7 @@ struct Tuned {
   uint32_t fanin;       // 0 = no entry
   uint32_t merge_tile;  // 0 = no entry
   uint32_t radix_tile;  // 0 = no entry
+  uint32_t handler;     // 0 = no entry
 };
 
 // Entry for (architecture of the current device, key width, values or not,

@@ -21,14 +21,14 @@ def u64(t: torch.Tensor) -> np.ndarray:
     return to_host(t).view(np.uint64) if t.dtype == torch.int64 else to_host(t)
 
 
-def run_gpu(keys, vals, P, s=0, mode=O.INV_COUNT, fanin=0, tile=0, ws=None, rtile=0):
+def run_gpu(keys, vals, P, s=0, mode=O.INV_COUNT, fanin=0, tile=0, ws=None, rtile=0, handler=0):
     kd = to_dev(keys)
     if vals is None:
         r = L.sort_keys(kd, P, s=s, investigator=mode, fanin=fanin, merge_tile=tile, want_send=True,
-                        want_cuts=True, workspace=ws, radix_tile=rtile)
+                        want_cuts=True, workspace=ws, radix_tile=rtile, handler=handler)
     else:
         r = L.sort_pairs(kd, to_dev(vals), P, s=s, investigator=mode, fanin=fanin, merge_tile=tile,
-                         want_send=True, want_cuts=True, workspace=ws, radix_tile=rtile)
+                         want_send=True, want_cuts=True, workspace=ws, radix_tile=rtile, handler=handler)
     L.check(r.workspace)
     return r
 
@@ -59,8 +59,8 @@ def compare(r: L.SortResult, o: O.SortResult, P: int, b: int = 0, seg=None):
         assert_same("cuts", u64(r.cuts)[b], o.cuts.astype(np.uint64))
 
 
-def check_case(keys, vals, P, s=0, mode=O.INV_COUNT, fanin=0, tile=0, ws=None, rtile=0):
+def check_case(keys, vals, P, s=0, mode=O.INV_COUNT, fanin=0, tile=0, ws=None, rtile=0, handler=0):
     o = O.sample_sort(keys, vals, P, s, mode)
-    r = run_gpu(keys, vals, P, s, mode, fanin, tile, ws, rtile)
+    r = run_gpu(keys, vals, P, s, mode, fanin, tile, ws, rtile, handler)
     compare(r, o, P)
     return r, o
