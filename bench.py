@@ -72,7 +72,7 @@ def kernel_bytes_per_launch(name, n, kb, vb):
     figure x keys); None for kernels whose work is metadata or depends on the
     data (the mid-size fix-up and the fallback passes, empty launches on
     uniform keys)."""
-    if name in ("onesweep", "merge", "group_fix", "small_sort"):
+    if name in ("onesweep", "merge", "group_fix", "small_sort", "presorted"):
         return n * 2 * (kb + vb)          # read key+value, write key+value
     if name == "hist":
         return n * kb                     # read keys once for all digit counts
@@ -241,6 +241,38 @@ def check_batch_on_device(plan, keys, seg, sizes, P):
         assert bool(ok.all()), "partition offsets differ from the count-based investigator"
 
 
+def presorted_keys(keys, sizes, P):
+    """Keys in blocks above 4096 keys, and of those the keys in blocks that
+    are already non-decreasing or non-increasing (uint32 keys, counted on the
+    device)."""
+    import numpy as np
+    import torch
+    sz = sizes.astype(np.int64)
+    seg = np.concatenate([[0], np.cumsum(sz)])
+    bounds = seg[:-1, None] + (np.arange(P + 1)[None, :] * sz[:, None]) // P      # [B, P+1]
+    starts = np.concatenate([bounds[:, :-1].reshape(-1), [seg[-1]]])           # [NB+1]
+    bsz = np.diff(starts)
+    st = torch.from_numpy(starts).to(keys.device)
+    NB = len(bsz)
+    up_bad = torch.zeros(NB, dtype=torch.int64, device=keys.device)
+    down_bad = torch.zeros_like(up_bad)
+    k = keys.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    total = k.numel()
+    CH = 1 << 27
+    for a in range(0, max(total - 1, 0), CH):
+        e = min(total - 1, a + CH)
+        x = torch.arange(a, e, device=keys.device, dtype=torch.int64)
+        blk = torch.searchsorted(st, x, right=True) - 1
+        inside = (x + 1) < st[blk + 1]
+        d = k[a + 1:e + 1] - k[a:e]
+        up_bad.index_add_(0, blk[inside], (d[inside] < 0).to(torch.int64))
+        down_bad.index_add_(0, blk[inside], (d[inside] > 0).to(torch.int64))
+        del x, blk, inside, d
+    pre = ((up_bad == 0) | (down_bad == 0)).cpu().numpy()
+    large = bsz > 4096
+    return int(bsz[large].sum()), int(bsz[large & pre].sum())
+
+
 def run_batch(args, steps, warmup, tune=True, check=True):
     """Batched form: B uneven u32 key/value instances (sizes log-uniform in
     [1K, 4M], uniform / normal / sorted / reverse keys), P = 8, sorted by one
@@ -257,13 +289,14 @@ def run_batch(args, steps, warmup, tune=True, check=True):
     keys, vals, seg, sizes = datagen.batch_u32_torch(B, 4, device="cuda")
     total = int(sizes.sum())
     tuned = None
-    if tune:
+    force = dict(fanin=args.fanin, merge_tile=args.merge_tile, radix_tile=args.radix_tile, handler=args.handler)
+    if tune and not any(force.values()):
         print("[bench] autotuning the batch", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         tuned = L.autotune(L.U32, L.VAL_U32, P, keys=keys, vals=vals, seg_offsets=seg)
         tuned["tuning_s"] = round(time.perf_counter() - t0, 2)
-    used = L.resolve_params(L.U32, L.VAL_U32, P, total, B=B)
-    plan = L.BatchPlan(keys, seg, P, vals=vals)
+    used = L.resolve_params(L.U32, L.VAL_U32, P, total, B=B, **force)
+    plan = L.BatchPlan(keys, seg, P, vals=vals, **force)
     for _ in range(warmup):
         plan.run()
     torch.cuda.synchronize()
@@ -295,10 +328,16 @@ def run_batch(args, steps, warmup, tune=True, check=True):
     plan.check()
     if check:
         check_batch_on_device(plan, keys, seg, sizes, P)
+    if args.no_loop:
+        return {"value": round(total / (ms_graph / 1e3) / 1e9, 4), "unit": "GKeys/s", "ms_per_step": round(ms_graph, 4),
+                "config": {"workload": f"batching: {B} instances (no per-instance loop)", "total_keys": total},
+                "settings": used, "graph_ms": round(ms_graph, 4),
+                "kernels": {k: {"launches": c, "ms": round(t, 5)} for k, (c, t) in prof.items()}}
     # the per-instance loop
     kout = torch.empty_like(keys)
     vout = torch.empty_like(vals)
-    prm = L.Params(P, 0, 0, used["fanin"], used["merge_tile"], used["radix_tile"], 0)
+    prm = L.Params(P, 0, 0, used["fanin"], used["merge_tile"], used["radix_tile"], used["handler"],
+                   used["presorted"], 0)
     offs = torch.empty((B, P + 1), dtype=torch.int64, device="cuda")
     need = ctypes.c_size_t(0)
     parts = L.Parts(offs.data_ptr(), 0, 0, 0, 0)
@@ -336,11 +375,13 @@ def run_batch(args, steps, warmup, tune=True, check=True):
     assert torch.equal(i32(kout), i32(plan.keys_out)) and torch.equal(i32(vout), i32(plan.vals_out)), \
         "loop and batch differ"
     assert torch.equal(offs, plan.part_offsets), "loop and batch partition offsets differ"
-    # roofline of the dominant kernel: onesweep covers the keys of blocks
-    # larger than one LDS sort (4096 keys), small_sort the others
-    bsz = np.diff((np.arange(P + 1)[None, :] * sizes.astype(np.int64)[:, None]) // P, axis=1)
-    n_large = int(bsz[bsz > 4096].sum())
-    n_of = lambda name: n_large if name in ("onesweep", "hist") else (total - n_large if name == "small_sort" else total)
+    # roofline of the dominant kernel: the histogram reads the keys of blocks
+    # larger than one LDS sort (4096 keys), small_sort sorts the others; of
+    # the large blocks, those already in order or in reverse order are copied
+    # (presorted) and the others take the radix passes (onesweep)
+    n_large, n_pre = presorted_keys(keys, sizes, P)
+    n_of = lambda name: {"onesweep": n_large - n_pre, "hist": n_large, "presorted": n_pre,
+                         "small_sort": total - n_large}.get(name, total)
     dom = max(((k, t) for k, (c, t) in prof.items() if kernel_bytes_per_launch(k, n_of(k), 4, 4)),
               key=lambda x: x[1])[0]
     c, t = prof[dom]
@@ -352,7 +393,8 @@ def run_batch(args, steps, warmup, tune=True, check=True):
         "value": round(value, 4), "unit": "GKeys/s", "ms_per_step": round(ms_graph, 4),
         "config": {"workload": f"batching: {B} uint32 key-value instances, sizes log-uniform in [1K, 4M], "
                                f"uniform/normal/sorted/reverse keys, P=8, one HIP-graph launch, autotuned",
-                   "instances": B, "total_keys": total, "P": P, "keys_in_blocks_above_4096": n_large},
+                   "instances": B, "total_keys": total, "P": P, "keys_in_blocks_above_4096": n_large,
+                   "keys_in_presorted_blocks": n_pre},
         "settings": used, "autotuned": tuned,
         "eager_ms": round(ms_eager, 4), "graph_ms": round(ms_graph, 4),
         "loop_ms": round(ms_loop, 4), "loop_wall_ms": round(wall_loop, 2),
@@ -608,7 +650,7 @@ def measure_sort(w, args, steps, warmup, profile=True, tune=False):
     ws = L.Workspace(dev)
     vt = (L.VAL_U32 if vals is not None else L.VAL_INDEX) if has_v else L.NOVAL
     tuned = None
-    if tune and not (args.fanin or args.merge_tile):
+    if tune and not (args.fanin or args.merge_tile or args.radix_tile or args.handler):
         print(f"[bench] autotuning {w['tag']}", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         tuned = L.autotune(L.key_code(keys.dtype), vt, w["P"], keys=keys, vals=vals)
@@ -617,9 +659,10 @@ def measure_sort(w, args, steps, warmup, profile=True, tune=False):
     def step():
         if not has_v:
             return L.sort_keys(keys, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
-                               keys_out=kout, workspace=ws)
+                               keys_out=kout, workspace=ws, radix_tile=args.radix_tile, handler=args.handler)
         return L.sort_pairs(keys, vals, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
-                            keys_out=kout, vals_out=vout, workspace=ws)
+                            keys_out=kout, vals_out=vout, workspace=ws, radix_tile=args.radix_tile,
+                            handler=args.handler)
 
     for _ in range(warmup):
         r = step()
@@ -652,7 +695,7 @@ def measure_sort(w, args, steps, warmup, profile=True, tune=False):
     imb = {"max_over_mean": round(float(counts.max() / counts.mean()), 6), "min": int(counts.min()),
            "max": int(counts.max()), "P": w["P"]}
     used = L.resolve_params(L.key_code(keys.dtype), vt, w["P"], w["n"], s=w["s"], fanin=args.fanin,
-                            merge_tile=args.merge_tile)
+                            merge_tile=args.merge_tile, radix_tile=args.radix_tile, handler=args.handler)
     out = dict(ms=ms, value=w["n"] / (ms / 1e3) / 1e9, prof=prof, ms_prof=ms_prof, imbalance=imb, settings=used,
                autotuned=tuned, kb=keys.element_size(), vb=4 if has_v else 0, dtype=KEY_NAMES[str(keys.dtype)])
     del keys, vals, kout, vout, ws, r
@@ -701,6 +744,9 @@ def main():
     ap.add_argument("--cpu-sample-one", type=int, default=1 << 24, help="keys of the one-thread oracle sample")
     ap.add_argument("--fanin", type=int, default=0)
     ap.add_argument("--merge-tile", type=int, default=0)
+    ap.add_argument("--radix-tile", type=int, default=0)
+    ap.add_argument("--handler", type=int, default=0, help="1: F-way passes, 2: one pass (0: tuned)")
+    ap.add_argument("--no-loop", action="store_true", help="batch: leave out the per-instance loop (profiling)")
     ap.add_argument("--batch", type=int, default=4096, help="instances for --workload batch")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests for --workload serve")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second (serve)")

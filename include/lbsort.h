@@ -102,12 +102,19 @@ typedef struct lbsort_params {
                             power of two reaching P (up to 64)                              */
   uint32_t merge_tile;   /* elements per merge tile: 0 = tuned, else 1024, 2048 or 4096
                             (LBSORT_HANDLER_ONE_PASS: 2048 or 4096, the tile's capacity)    */
-  uint32_t radix_tile;   /* keys per radix tile of the local sort: 0 = tuned, else 4096 or
-                            8192 (digits are 8 bits wide in every case)                     */
+  uint32_t radix_tile;   /* keys per radix tile of the local sort: 0 = tuned, else 4096,
+                            8192 or, for 32-bit keys, 16384 (digits are 8 bits wide in
+                            every case)                                                     */
   uint32_t handler;      /* step 6: 0 = tuned, LBSORT_HANDLER_PASSES or
                             LBSORT_HANDLER_ONE_PASS                                         */
+  uint32_t presorted;    /* step 1: 0 = tuned, LBSORT_PRESORTED_DETECT (blocks already in
+                            order or in reverse order skip the radix passes; the default)
+                            or LBSORT_PRESORTED_IGNORE                                      */
   uint32_t reserved;     /* must be 0                                                        */
 } lbsort_params;
+
+#define LBSORT_PRESORTED_DETECT 1
+#define LBSORT_PRESORTED_IGNORE 2
 
 /* Handler (step 6, Section IV.A, Fig. 2) schedules.  Both merge each
  * partition's P runs stably (ties to the lower block) and give the same bytes.
@@ -254,11 +261,11 @@ const char *lbsort_last_error(void);
  * the current device and records the fastest in the tuning cache, keyed by
  * the device architecture, the key width, values or not, the instance size
  * (total_n / B, to a power of two), batched or not, and P.  Searched: the
- * radix tile (4096, 8192) and the handler schedule (LBSORT_HANDLER_PASSES
+ * radix tile (4096, 8192, and 16384 for 32-bit keys) and the handler schedule (LBSORT_HANDLER_PASSES
  * with each fan-in F = 2 .. 16 up to the power of two above P, and
  * LBSORT_HANDLER_ONE_PASS where it applies) with the default merge tile, then
  * the merge tile (1024, 2048, 4096; 2048 or 4096 for one pass) with the best
- * of those.  Every candidate must produce
+ * of those, then whether presorted blocks are looked for.  Every candidate must produce
  * the same bytes (keys, values, part_offsets) as the first, else
  * LBSORT_ERR_DEVICE.  The radix digit is 8 bits wide in every case.
  *
@@ -282,9 +289,9 @@ int lbsort_load_tuning(const char *cache_path);
 /*
  * The settings a sort call with these arguments would run with on the
  * current device (host only, nothing enqueued): P, s (the default budget
- * resolved), investigator, and fanin / merge_tile / radix_tile / handler as
- * given, else from the tuning cache, else the defaults.  out (host) receives
- * them.
+ * resolved), investigator, and fanin / merge_tile / radix_tile / handler /
+ * presorted as given, else from the tuning cache, else the defaults.  out
+ * (host) receives them.
  */
 int lbsort_resolve_params(int key_type, int val_type, uint32_t B, uint64_t total_n,
                           const lbsort_params *params, lbsort_params *out);

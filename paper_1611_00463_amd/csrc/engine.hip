@@ -22,6 +22,8 @@ void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo = 0);
 template <typename K, bool HASV>
 void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s);
 template <typename K, bool HASV>
+void launch_presorted(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s);
+template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s);
 template <bool HASV>
 void launch_group_fix(const Plan& p, const u64* src, const u32* srcv, u64* dst, u32* dstv, hipStream_t s);
@@ -121,6 +123,7 @@ struct Shape {
   u64 mtiles;       // merge tiles of one pass, worst case
   bool local_only;  // step 1 only
   u32 handler;      // LBSORT_HANDLER_PASSES or LBSORT_HANDLER_ONE_PASS
+  u32 presort;      // LBSORT_PRESORTED_DETECT or LBSORT_PRESORTED_IGNORE
   // one-pass handler: the sample problem (sample slots with gaps between
   // instances, its multi-pass merge: fan-in, tile, passes, groups, tiles)
   u64 s_max;
@@ -130,7 +133,7 @@ struct Shape {
 };
 
 struct Layout {
-  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, tdesc, gflags, gflags2, midlist, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
+  u64 counters, blk_start, tstart, small_list, large_list, rem_prefix, tdesc, gflags, gflags2, presorted, midlist, samp_start, hist, status, samples, pool, lo, hi, cuts, Dm, G,
       splitters, mtile, rec_start, rec_end, rec_out, rec_n, slot_grp, grp_run, grp_out, tmpk, tmpv, seg, total;
   // one-pass handler
   u64 sseg, sbs, scuts, sDm, gsbase, ntile, skeys[2], svals[2], s_mtile, s_rec_start, s_rec_end, s_rec_out, s_rec_n,
@@ -165,6 +168,7 @@ static Layout make_layout(const Shape& sh) {
   l.tdesc = take(sh.max_tiles * sizeof(TileDesc));
   l.gflags = take(NB * 4);
   l.gflags2 = take(NB * 4);
+  l.presorted = take(NB * 4);
   l.midlist = take(mid_cap(sh) * 8);
   l.samples = take(sh.max_samples * K);
   l.pool = take(sh.max_samples * K);
@@ -220,11 +224,14 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
                 val_type);
   if (val_type == LBSORT_VAL_INDEX && B == 1 && total_n > (1ull << 32))
     return fail(LBSORT_ERR_UNSUPPORTED, "LBSORT_VAL_INDEX needs n <= 2^32 (32-bit positions)");
-  lbsort_params d = {1, 0, LBSORT_INV_COUNT, 0, 0, 0, 0, 0};
+  lbsort_params d = {1, 0, LBSORT_INV_COUNT, 0, 0, 0, 0, 0, 0};
   const lbsort_params& p = prm ? *prm : d;
   if (p.P < 1 || p.P > LBSORT_MAX_P) return fail(LBSORT_ERR_INVALID_ARG, "P must be in [1, %d] (got %u)", LBSORT_MAX_P, p.P);
   if (p.investigator > 2) return fail(LBSORT_ERR_INVALID_ARG, "unknown investigator mode %u", p.investigator);
   if (p.s > LBSORT_MAX_SAMPLES) return fail(LBSORT_ERR_INVALID_ARG, "s must be <= %u (got %u)", LBSORT_MAX_SAMPLES, p.s);
+  if (p.presorted > LBSORT_PRESORTED_IGNORE)
+    return fail(LBSORT_ERR_INVALID_ARG, "presorted must be 0, LBSORT_PRESORTED_DETECT or LBSORT_PRESORTED_IGNORE (got %u)",
+                p.presorted);
   if (p.handler > LBSORT_HANDLER_ONE_PASS)
     return fail(LBSORT_ERR_INVALID_ARG, "handler must be 0, LBSORT_HANDLER_PASSES or LBSORT_HANDLER_ONE_PASS (got %u)",
                 p.handler);
@@ -233,9 +240,10 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
     return fail(LBSORT_ERR_INVALID_ARG, "fanin must be 0, 2, 4, 8 or 16 (got %u)", p.fanin);
   if (p.merge_tile != 0 && p.merge_tile != 1024 && p.merge_tile != 2048 && p.merge_tile != 4096)
     return fail(LBSORT_ERR_INVALID_ARG, "merge_tile must be 0, 1024, 2048 or 4096 (got %u)", p.merge_tile);
-  if (p.radix_tile != 0 && p.radix_tile != RTILE_SMALL && p.radix_tile != RTILE_LARGE)
-    return fail(LBSORT_ERR_INVALID_ARG, "radix_tile must be 0, %u or %u (got %u)", RTILE_SMALL, RTILE_LARGE,
-                p.radix_tile);
+  if (p.radix_tile != 0 && p.radix_tile != RTILE_SMALL && p.radix_tile != RTILE_LARGE &&
+      !(p.radix_tile == RTILE_HUGE && key_width(key_type) == 4))
+    return fail(LBSORT_ERR_INVALID_ARG, "radix_tile must be 0, %u, %u or (32-bit keys) %u (got %u)", RTILE_SMALL,
+                RTILE_LARGE, RTILE_HUGE, p.radix_tile);
   if (p.reserved != 0) return fail(LBSORT_ERR_INVALID_ARG, "reserved must be 0");
   if (B < 1) return fail(LBSORT_ERR_INVALID_ARG, "B must be >= 1");
   if (total_n >= (1ull << 44)) return fail(LBSORT_ERR_UNSUPPORTED, "total_n must be < 2^44");
@@ -296,6 +304,8 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   }
   sh.F = F;
   sh.rtile = p.radix_tile ? p.radix_tile : (tu.radix_tile ? tu.radix_tile : RTILE_LARGE);
+  sh.presort = p.presorted ? p.presorted : (tu.presorted ? tu.presorted : LBSORT_PRESORTED_DETECT);
+  if (sh.rtile == RTILE_HUGE && kb != 4) sh.rtile = RTILE_LARGE;  // a tuned entry of another key width
   u32 L = 0;
   for (u64 span = 1; span < p.P; span *= F) ++L;
   sh.L = local_only ? 0 : L;
@@ -373,6 +383,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.tdesc = (TileDesc*)(ws + lay.tdesc);
   p.gflags = (u32*)(ws + lay.gflags);
   p.gflags2 = (u32*)(ws + lay.gflags2);
+  u32* const presorted = (u32*)(ws + lay.presorted);
   p.midlist = (u64*)(ws + lay.midlist);
   p.mid_cap = mid_cap(sh);
   p.counters = (u32*)(ws + lay.counters);
@@ -424,6 +435,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   if (sh.has_large) {
     launch_fill32(p.hist, (u64)p.NB * sh.D * RADIX, 0, st);
     launch_fill32((u32*)p.status, sh.max_tiles * RADIX * 2, 0, st);
+    if (sh.presort == LBSORT_PRESORTED_DETECT) launch_fill32(presorted, p.NB, 3u, st);
   }
   launch_plan(p, st);
   // the fix-up path of 64-bit keys needs the counts of the three top digits only
@@ -434,7 +446,23 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
     ph.run_slot = C_RUN_TOP;
     ph.run_mask = 0xE0u;  // digits 5, 6, 7
   }
-  if (sh.has_large) launch_hist<K>(hybrid ? ph : px, kin, st, hybrid ? 5u : 0u);
+  if (sh.has_large) {
+    // the histogram also finds the large blocks that are already in order
+    // (or in reverse order); those are written to the local sort's output
+    // at once, and the radix passes are planned again without them
+    const bool detect = sh.presort == LBSORT_PRESORTED_DETECT;
+    Plan hp = hybrid ? ph : px;
+    hp.presorted = detect ? presorted : nullptr;
+    launch_hist<K>(hp, kin, st, hybrid ? 5u : 0u);
+    if (detect) {
+      Plan cp = px;
+      cp.presorted = presorted;
+      launch_presorted<K, HASV>(cp, kin, vin, dk(sh.D - 1), dv(sh.D - 1), st);
+      Plan rp = p;
+      rp.skip = presorted;
+      launch_plan(rp, st);
+    }
+  }
   if (sh.has_small) launch_small_sort<K, HASV>(px, kin, vin, dk(sh.D - 1), dv(sh.D - 1), st);
   if (sh.has_large) {
     if constexpr (sizeof(K) == 8) {
@@ -674,7 +702,7 @@ int lbsort_resolve_params(int key_type, int val_type, uint32_t B, uint64_t total
   Shape sh;
   int rc = make_shape(key_type, val_type, B, total_n, params, false, sh);
   if (rc) return rc;
-  lbsort_params r = {sh.P, sh.s, sh.inv, sh.F, sh.TM, sh.rtile, sh.handler, 0};
+  lbsort_params r = {sh.P, sh.s, sh.inv, sh.F, sh.TM, sh.rtile, sh.handler, sh.presort, 0};
   *out = r;
   return LBSORT_OK;
 }

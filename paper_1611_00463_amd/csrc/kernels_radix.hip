@@ -87,7 +87,8 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
     }
     // with a filter, only the listed large blocks are planned (small blocks
     // and sample offsets are unaffected by it)
-    const bool keep = p.only == nullptr || (idx < p.NB && p.only[idx] != 0);
+    const bool keep = (p.only == nullptr || (idx < p.NB && p.only[idx] != 0)) &&
+                      (p.skip == nullptr || (idx < p.NB && p.skip[idx] == 0));
     const u64 tiles = (keep && n > (u64)SMALL_TILE) ? (n + p.rtile - 1) / p.rtile : 0;
     const u64 smp = n < (u64)p.s ? n : (u64)p.s;
     const u64 small = (p.only == nullptr && n > 0 && n <= (u64)SMALL_TILE) ? 1 : 0;
@@ -213,9 +214,20 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
   u32 blk = s_blk;
   K hot = 0;
   bool have_hot = false;
+  // Presorted blocks: every pair of neighbours inside the block is compared;
+  // a pair out of non-decreasing order clears bit 0 of the block's flag, one
+  // out of non-increasing order bit 1 (one atomic per wave and block).
+  bool up_ok = true, down_ok = true;
+  auto flush_order = [&](u32 b) {
+    if (p.presorted == nullptr) return;
+    const u32 clear = (__ballot(!up_ok) ? 1u : 0u) | (__ballot(!down_ok) ? 2u : 0u);
+    if (clear && lane == 0) atomicAnd(&p.presorted[b], ~clear);
+    up_ok = down_ok = true;
+  };
   for (u32 t = t_begin; t < t_end; ++t) {
     if (t >= p.tstart[blk + 1]) {
       // next block: flush the counts of this one
+      flush_order(blk);
       __syncthreads();
       u32* gh = p.hist + (u64)blk * D * RADIX;
       for (int i = tid; i < D * RADIX; i += SORT_NT) {
@@ -231,20 +243,38 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
     // the tile's keys are read HB at a time, all loads in flight together
     // (a load and its use in one step made every key wait on memory alone)
     constexpr int HB = 8;
-    static_assert((RTILE_SMALL / SORT_NT) % HB == 0 && (RTILE_LARGE / SORT_NT) % HB == 0, "whole load batches");
+    static_assert((RTILE_SMALL / SORT_NT) % HB == 0 && (RTILE_LARGE / SORT_NT) % HB == 0 &&
+                  (RTILE_HUGE / SORT_NT) % HB == 0, "whole load batches");
     const int per_thread = (int)(p.rtile / SORT_NT);
     for (int j0 = 0; j0 < per_thread; j0 += HB) {
-    K kb[HB];
+    // order checks only while some lane of the wave has not yet seen a pair
+    // out of each order (random keys stop checking after a few keys)
+    const bool chk = p.presorted != nullptr && __ballot(up_ok || down_ok) != 0;
+    K kb[HB], kn[HB];
 #pragma unroll
     for (int u = 0; u < HB; ++u) {
       const u32 idx = (j0 + u) * SORT_NT + tid;
       kb[u] = src[tbase + (idx < tile_n ? idx : 0)];  // clamped: tile_n >= 1
+      // the last lane of a wave also needs the key after its own (the next
+      // wave's first, or the next tile's): loaded with the others
+      kn[u] = (chk && lane == 63 && (u64)idx + 1 < rem) ? src[tbase + idx + 1] : (K)0;
     }
 #pragma unroll
     for (int u = 0; u < HB; ++u) {
       const u32 idx = (j0 + u) * SORT_NT + tid;
       const bool valid = idx < tile_n;
       const K key = valid ? key_in<K>(kb[u], p.kx_top, p.kx_fm) : (K)0;
+      if (chk) {
+        // the key at idx + 1: the next lane's, or for the last lane of the
+        // wave a load (the next wave's first key, or the next tile's)
+        K nxt = __shfl_down(key, 1);
+        const bool pair = (u64)idx + 1 < rem;
+        if (lane == 63) nxt = key_in<K>(kn[u], p.kx_top, p.kx_fm);
+        if (valid && pair) {
+          up_ok = up_ok && key <= nxt;
+          down_ok = down_ok && key >= nxt;
+        }
+      }
       bool done = !valid;
       if (have_hot) {
         // the wave's hot key (a value seen in many lanes before) first
@@ -304,10 +334,66 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
     }
     }
   }
+  flush_order(blk);
   __syncthreads();
   u32* gh = p.hist + (u64)blk * D * RADIX;
   for (int i = tid; i < D * RADIX; i += SORT_NT)
     if (h[i]) atomicAdd(&gh[i], h[i]);
+}
+
+// Presorted large blocks (step 1 needs no radix pass for them; TimSort's runs
+// are the same idea): one workgroup per radix tile of the full plan writes the
+// tile's keys (mapped to the unsigned order) and values to the local sort's
+// output.  A non-decreasing block is copied; a non-increasing one is reversed
+// run by run: the key at block position x whose run of equal keys is [a, b)
+// goes to n - b + (x - a), which keeps equal keys in input order (stable).
+// Runs are found from the neighbours in the common case of distinct keys, by
+// binary search in the block otherwise.  Tiles of other blocks leave at once.
+template <typename K, bool HASV>
+__global__ __launch_bounds__(256) void k_presorted(Plan p, const K* __restrict__ src, const u32* __restrict__ srcv,
+                                                   K* __restrict__ dst, u32* __restrict__ dstv) {
+  const u32 t = blockIdx.x, tid = threadIdx.x;
+  if (t >= p.tstart[p.NB]) return;
+  const u32 blk = find_seg(p.tstart, p.NB, t);
+  const u32 f = p.presorted[blk];
+  if (f == 0) return;
+  const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
+  const u64 tbase = bs + (u64)(t - p.tstart[blk]) * p.rtile;
+  const u32 tile_n = be - tbase < (u64)p.rtile ? (u32)(be - tbase) : p.rtile;
+  const u64 vgen = bs - p.seg[blk / p.P];  // generated values: input position inside the instance
+  const u64 n = be - bs;
+  for (u32 i = tid; i < tile_n; i += 256) {
+    const u64 x = tbase + i;
+    const K k = key_in<K>(src[x], p.kx_top, p.kx_fm);
+    u32 v = 0;
+    if (HASV) v = srcv != nullptr ? srcv[x] : (u32)(vgen + (x - bs));
+    u64 o = x;
+    if ((f & 1u) == 0) {
+      // non-increasing: the run of k is [a, b) (block-relative)
+      const u64 xr = x - bs;
+      const bool eq_prev = xr > 0 && key_in<K>(src[x - 1], p.kx_top, p.kx_fm) == k;
+      const bool eq_next = xr + 1 < n && key_in<K>(src[x + 1], p.kx_top, p.kx_fm) == k;
+      u64 a = xr, b = xr + 1;
+      if (eq_prev || eq_next) {
+        // keys above k come first, then the run of k, then keys below it
+        u64 lo = 0, hi = n;
+        while (lo < hi) {
+          const u64 mid = lo + ((hi - lo) >> 1);
+          if (key_in<K>(src[bs + mid], p.kx_top, p.kx_fm) > k) lo = mid + 1; else hi = mid;
+        }
+        a = lo;
+        hi = n;
+        while (lo < hi) {
+          const u64 mid = lo + ((hi - lo) >> 1);
+          if (key_in<K>(src[bs + mid], p.kx_top, p.kx_fm) >= k) lo = mid + 1; else hi = mid;
+        }
+        b = lo;
+      }
+      o = bs + (n - b) + (xr - a);
+    }
+    dst[o] = k;
+    if (HASV) dstv[o] = v;
+  }
 }
 
 // Exclusive scan of the 256 counts of every (block, pass): digit start offsets.
@@ -392,7 +478,8 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
                                                  u32* __restrict__ dstv0, u32 pass) {
   constexpr int NWV = NT / 64, WI = 64 * ITEMS;
   constexpr u32 TILE = NT * ITEMS;  // the launch passes this kernel only calls whose p.rtile == TILE
-  static_assert(TILE == RTILE_SMALL || TILE == RTILE_LARGE, "radix tiles of RTILE_SMALL or RTILE_LARGE keys");
+  static_assert(TILE == RTILE_SMALL || TILE == RTILE_LARGE || (TILE == RTILE_HUGE && sizeof(K) == 4),
+                "radix tiles of RTILE_SMALL or RTILE_LARGE keys, RTILE_HUGE for 32-bit keys");
   static_assert(NT >= RADIX, "one thread per digit");
   // LDS: 16-bit per-wave digit counters (they end up holding the tile-local
   // start of each wave's run of a digit), 32-bit block-relative write bases,
@@ -1332,6 +1419,14 @@ void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo) {
 }
 
 template <typename K, bool HASV>
+void launch_presorted(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s) {
+  if (p.max_tiles == 0) return;
+  const int pe_ = prof_begin(s);
+  hipLaunchKernelGGL((k_presorted<K, HASV>), dim3(p.max_tiles), dim3(256), 0, s, p, src, srcv, dst, dstv);
+  prof_end(pe_, "presorted", s);
+}
+
+template <typename K, bool HASV>
 void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s) {
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_small_sort<K, HASV>), dim3(p.NB), dim3(SORT_NT), 0, s, p, src, srcv, dst, dstv); prof_end(pe_, "small_sort", s); }
 }
@@ -1339,15 +1434,28 @@ void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32
 template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s) {
   if (p.max_tiles == 0) return;
-  // Persistent grid, 8 keys per thread: tiles of 8192 keys take one
-  // 1024-thread workgroup per compute unit (about 105 KB of LDS for 64-bit
-  // keys with values), tiles of 4096 keys two 512-thread workgroups; a
-  // multiple of the queue count.
-  const u32 NT = p.rtile / 8;
+  // Persistent grid: tiles of 8192 keys take one 1024-thread workgroup per
+  // compute unit (8 keys per thread; about 105 KB of LDS for 64-bit keys with
+  // values), tiles of 4096 keys two 512-thread workgroups, and tiles of 16384
+  // 32-bit keys one 1024-thread workgroup with 16 keys per thread (about
+  // 137 KB with values); a multiple of the queue count.
+  const u32 NT = p.rtile == RTILE_HUGE ? 1024 : p.rtile / 8;
   u32 grid = p.persist_wgs * 256 / NT;
   grid = grid < p.max_tiles ? grid : p.max_tiles;
   grid = (grid + p.nq - 1) / p.nq * p.nq;
   const int pe_ = prof_begin(s);
+  if constexpr (sizeof(K) == 4) {
+    if (p.rtile == RTILE_HUGE) {
+      if (p.only)
+        hipLaunchKernelGGL((k_onesweep<K, HASV, 1024, 16, 1, true>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst, dstv,
+                           pass);
+      else
+        hipLaunchKernelGGL((k_onesweep<K, HASV, 1024, 16, 1, false>), dim3(grid), dim3(NT), 0, s, p, src, srcv, dst,
+                           dstv, pass);
+      prof_end(pe_, p.only ? "onesweep_fallback" : "onesweep", s);
+      return;
+    }
+  }
   if (p.rtile == RTILE_SMALL) {
     if (p.only)
       hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_SMALL / 8, 8, 2, true>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
@@ -1368,6 +1476,8 @@ void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* 
 
 #define LBS_INST(K)                                                                                     \
   template void launch_hist<K>(const Plan&, const K*, hipStream_t, u32);                                   \
+  template void launch_presorted<K, false>(const Plan&, const K*, const u32*, K*, u32*, hipStream_t);  \
+  template void launch_presorted<K, true>(const Plan&, const K*, const u32*, K*, u32*, hipStream_t);   \
   template void launch_small_sort<K, false>(const Plan&, const K*, const u32*, K*, u32*, hipStream_t); \
   template void launch_small_sort<K, true>(const Plan&, const K*, const u32*, K*, u32*, hipStream_t);  \
   template void launch_onesweep<K, false>(const Plan&, const K*, const u32*, K*, u32*, u32, hipStream_t); \

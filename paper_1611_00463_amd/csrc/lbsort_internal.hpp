@@ -12,8 +12,9 @@ typedef uint64_t u64;
 
 // Radix sort geometry (step 1): 8-bit digits.  Blocks of at most SMALL_TILE
 // keys are sorted whole in LDS (SORT_NT threads x SORT_ITEMS keys); larger
-// blocks are cut into radix tiles of Plan::rtile keys, RTILE_SMALL or
-// RTILE_LARGE (a call's choice, the same for all its passes).
+// blocks are cut into radix tiles of Plan::rtile keys, RTILE_SMALL,
+// RTILE_LARGE or (32-bit keys) RTILE_HUGE (a call's choice, the same for all
+// its passes).
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SORT_NT = 256;
@@ -21,6 +22,7 @@ constexpr int SORT_ITEMS = 16;
 constexpr int SMALL_TILE = SORT_NT * SORT_ITEMS;  // 4096 keys
 constexpr u32 RTILE_SMALL = 4096;
 constexpr u32 RTILE_LARGE = 8192;
+constexpr u32 RTILE_HUGE = 16384;  // 32-bit keys only (the staged tile fills most of the LDS)
 constexpr int WAVE = 64;
 // Group fix-up of the 64-bit local sort: groups of at most GF_HALO keys are
 // ranked in place; in the blocks that have larger groups of different keys,
@@ -78,7 +80,7 @@ struct Plan {
   u32 inv;               // investigator mode
   u32 F, L, TM;          // merge fan-in, merge levels, merge tile
   u32 max_tiles;         // radix tiles, worst case
-  u32 rtile;             // keys per radix tile: RTILE_SMALL or RTILE_LARGE
+  u32 rtile;             // keys per radix tile: RTILE_SMALL, RTILE_LARGE or RTILE_HUGE
   u32 nq;                // radix tile queues (NQ, or 1)
   u32 persist_wgs;       // workgroups of the persistent radix pass
   u64 total_n;
@@ -90,6 +92,9 @@ struct Plan {
   u32* rem_prefix;       // [NB+1] over large blocks: prefix of (tiles - C_RMIN)
   TileDesc* tdesc;       // [max_tiles] by status slot (queue base + ticket)
   const u32* only;       // [NB] or null: plan only the large blocks with only[b] != 0
+  const u32* skip;       // [NB] or null: leave out the large blocks with skip[b] != 0
+  u32* presorted;        // [NB] or null: bit 0 = the block is non-decreasing, bit 1 =
+                         // non-increasing (set to 3 before k_hist, which clears bits)
   u32 epoch_base;        // added to the look-back epochs of the radix passes
   u32* gflags;           // [NB] blocks the group fix-up could not finish
   u32* gflags2;          // [NB] blocks the mid-size group fix-up could not finish either

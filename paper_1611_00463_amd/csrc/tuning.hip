@@ -22,7 +22,7 @@ namespace lbs {
 
 struct Entry {
   std::string arch;  // e.g. "gfx950"
-  uint32_t key_bytes, values, size_log2, batched, P, fanin, merge_tile, radix_tile, handler;
+  uint32_t key_bytes, values, size_log2, batched, P, fanin, merge_tile, radix_tile, handler, presorted;
   double ms;
 };
 
@@ -77,7 +77,7 @@ static int parse_file(const char* path, std::vector<Entry>& out) {
   while ((r = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, r);
   fclose(f);
   // One object per entry: {"arch": "..", "key_bytes": .., "values": .., "size_log2": .., "batched": ..,
-  // "P": .., "fanin": .., "merge_tile": .., "radix_tile": .., "handler": .., "ms": ..}
+  // "P": .., "fanin": .., "merge_tile": .., "radix_tile": .., "handler": .., "presorted": .., "ms": ..}
   size_t pos = 0;
   while ((pos = s.find('{', pos + 1)) != std::string::npos) {
     size_t end = s.find('}', pos);
@@ -100,13 +100,13 @@ static int parse_file(const char* path, std::vector<Entry>& out) {
       return true;
     };
     std::string arch;
-    double kb, vt, sl, b, P, F, T, R, H, ms = 0;
+    double kb, vt, sl, b, P, F, T, R, H, S, ms = 0;
     if (str("arch", arch) && num("key_bytes", kb) && num("values", vt) && num("size_log2", sl) &&
         num("batched", b) && num("P", P) && num("fanin", F) && num("merge_tile", T) && num("radix_tile", R) &&
-        num("handler", H)) {
+        num("handler", H) && num("presorted", S)) {
       num("ms", ms);
       out.push_back(Entry{arch, (uint32_t)kb, (uint32_t)vt, (uint32_t)sl, (uint32_t)b, (uint32_t)P, (uint32_t)F,
-                          (uint32_t)T, (uint32_t)R, (uint32_t)H, ms});
+                          (uint32_t)T, (uint32_t)R, (uint32_t)H, (uint32_t)S, ms});
     }
     pos = end;
   }
@@ -121,9 +121,10 @@ static int write_file(const char* path) {
     const Entry& e = g_table[i];
     fprintf(f,
             "  {\"arch\": \"%s\", \"key_bytes\": %u, \"values\": %u, \"size_log2\": %u, \"batched\": %u, \"P\": %u, "
-            "\"fanin\": %u, \"merge_tile\": %u, \"radix_tile\": %u, \"handler\": %u, \"ms\": %.4f}%s\n",
+            "\"fanin\": %u, \"merge_tile\": %u, \"radix_tile\": %u, \"handler\": %u, \"presorted\": %u, "
+            "\"ms\": %.4f}%s\n",
             e.arch.c_str(), e.key_bytes, e.values, e.size_log2, e.batched, e.P, e.fanin, e.merge_tile, e.radix_tile,
-            e.handler, e.ms, i + 1 < g_table.size() ? "," : "");
+            e.handler, e.presorted, e.ms, i + 1 < g_table.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -152,7 +153,7 @@ Tuned tuning_lookup(uint32_t key_bytes, bool values, uint64_t n, uint32_t B, uin
         for (auto& e : v) upsert(e);
     }
   }
-  Tuned t = {0, 0, 0, 0};
+  Tuned t = {0, 0, 0, 0, 0};
   if (arch.empty()) return t;
   const uint32_t sc = size_class(n);
   const uint32_t batched = B > 1 ? 1 : 0;
@@ -168,6 +169,7 @@ Tuned tuning_lookup(uint32_t key_bytes, bool values, uint64_t n, uint32_t B, uin
     t.merge_tile = best->merge_tile;
     t.radix_tile = best->radix_tile;
     t.handler = best->handler;
+    t.presorted = best->presorted;
   }
   return t;
 }
@@ -234,7 +236,9 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
   uint32_t pow2P = 2;
   while (pow2P < P) pow2P *= 2;
   if (one_ok) scheds.push_back(Sched{LBSORT_HANDLER_ONE_PASS, pow2P});
-  const uint32_t rtiles[2] = {4096, 8192}, mtiles[3] = {1024, 2048, 4096};
+  std::vector<uint32_t> rtiles = {4096, 8192};
+  if (kb == 4) rtiles.push_back(16384);  // 32-bit keys also take tiles of 16384 keys
+  const uint32_t mtiles[3] = {1024, 2048, 4096};
   void *kin = nullptr, *kout = nullptr, *kref = nullptr, *ws = nullptr;
   uint32_t *vin = nullptr, *vout = nullptr, *vref = nullptr;
   uint64_t *seg = nullptr, *offs = nullptr, *oref = nullptr;
@@ -244,13 +248,13 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
   int rc = LBSORT_OK;
   size_t ws_need = 0;
   double best_ms = 1e30;
-  uint32_t best_f = 0, best_t = 0, best_r = 0, best_h = 0;
+  uint32_t best_f = 0, best_t = 0, best_r = 0, best_h = 0, best_s = LBSORT_PRESORTED_DETECT;
   bool have_ref = false;
   lbsort_parts parts;
   memset(&parts, 0, sizeof parts);
   const uint64_t noffs = (uint64_t)B * (P + 1);
-  auto measure = [&](uint32_t R, Sched h, uint32_t T) -> int {
-    lbsort_params prm = {P, 0, LBSORT_INV_COUNT, h.fanin, T, R, h.handler, 0};
+  auto measure = [&](uint32_t R, Sched h, uint32_t T, uint32_t S) -> int {
+    lbsort_params prm = {P, 0, LBSORT_INV_COUNT, h.fanin, T, R, h.handler, S, 0};
     size_t wsb = ws_need;
     float times[5];
     for (int it = 0; it < 6; ++it) {
@@ -291,6 +295,7 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
       best_t = T;
       best_r = R;
       best_h = h.handler;
+      best_s = S;
     }
     return LBSORT_OK;
   };
@@ -298,7 +303,7 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
     for (Sched h : scheds)
       for (uint32_t T : mtiles) {
         if (h.handler == LBSORT_HANDLER_ONE_PASS && T < 2048) continue;
-        lbsort_params prm = {P, 0, LBSORT_INV_COUNT, h.fanin, T, R, h.handler, 0};
+        lbsort_params prm = {P, 0, LBSORT_INV_COUNT, h.fanin, T, R, h.handler, 0, 0};
         size_t need = 0;
         parts.part_offsets = (uint64_t*)1;  // the size query reads no pointer
         rc = lbsort_sort_batch(key_type, val_type, nullptr, nullptr, nullptr, nullptr, (const uint64_t*)1, B, total_n,
@@ -344,23 +349,31 @@ extern "C" int lbsort_autotune(int key_type, int val_type, const void* keys_in, 
   parts.part_offsets = offs;
   for (uint32_t R : rtiles)
     for (Sched h : scheds)
-      if ((rc = measure(R, h, h.handler == LBSORT_HANDLER_ONE_PASS ? 4096 : 2048)) != LBSORT_OK) goto done;
+      if ((rc = measure(R, h, h.handler == LBSORT_HANDLER_ONE_PASS ? 4096 : 2048, LBSORT_PRESORTED_DETECT)) !=
+          LBSORT_OK)
+        goto done;
   {
     const uint32_t R = best_r, T0 = best_t;
     const Sched h = {best_h, best_f};
     for (uint32_t T : mtiles)
-      if (T != T0 && !(h.handler == LBSORT_HANDLER_ONE_PASS && T < 2048) && (rc = measure(R, h, T)) != LBSORT_OK)
+      if (T != T0 && !(h.handler == LBSORT_HANDLER_ONE_PASS && T < 2048) &&
+          (rc = measure(R, h, T, LBSORT_PRESORTED_DETECT)) != LBSORT_OK)
         goto done;
+  }
+  {
+    // the same settings without looking for presorted blocks
+    const Sched h = {best_h, best_f};
+    if ((rc = measure(best_r, h, best_t, LBSORT_PRESORTED_IGNORE)) != LBSORT_OK) goto done;
   }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     upsert(Entry{arch, (uint32_t)kb, hasv ? 1u : 0u, size_class(total_n / B), B > 1 ? 1u : 0u, P, best_f, best_t,
-                 best_r, best_h, best_ms});
+                 best_r, best_h, best_s, best_ms});
     const char* path = (cache_path && *cache_path) ? cache_path : getenv("LBSORT_TUNE_CACHE");
     if (path && *path && write_file(path) != 0) rc = LBSORT_ERR_INVALID_ARG;
   }
   if (chosen) {
-    lbsort_params c = {P, 0, LBSORT_INV_COUNT, best_f, best_t, best_r, best_h, 0};
+    lbsort_params c = {P, 0, LBSORT_INV_COUNT, best_f, best_t, best_r, best_h, best_s, 0};
     *chosen = c;
   }
 done:

@@ -10,6 +10,7 @@ struct Tuned {
   uint32_t merge_tile;  // 0 = no entry
   uint32_t radix_tile;  // 0 = no entry
   uint32_t handler;     // 0 = no entry
+  uint32_t presorted;   // 0 = no entry
 };
 
 // Entry for (architecture of the current device, key width, values or not,

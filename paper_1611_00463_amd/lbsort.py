@@ -20,6 +20,7 @@ U32, U64, I32, I64, F32, F64 = 1, 2, 3, 4, 5, 6
 NOVAL, VAL_U32, VAL_INDEX = 0, 1, 2
 INV_COUNT, INV_NONE, INV_PAPER = 0, 1, 2
 HANDLER_PASSES, HANDLER_ONE_PASS = 1, 2
+PRESORTED_DETECT, PRESORTED_IGNORE = 1, 2
 OK = 0
 ERR_INVALID_ARG, ERR_WORKSPACE_TOO_SMALL, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM, ERR_DEVICE = -1, -2, -3, -4, -5, -6
 
@@ -29,7 +30,7 @@ _c_u64p = ctypes.POINTER(ctypes.c_uint64)
 class Params(ctypes.Structure):
     _fields_ = [("P", ctypes.c_uint32), ("s", ctypes.c_uint32), ("investigator", ctypes.c_uint32),
                 ("fanin", ctypes.c_uint32), ("merge_tile", ctypes.c_uint32), ("radix_tile", ctypes.c_uint32),
-                ("handler", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("handler", ctypes.c_uint32), ("presorted", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Parts(ctypes.Structure):
@@ -135,8 +136,8 @@ class Workspace:
         return self.buf
 
 
-def _params(P, s, investigator, fanin, merge_tile, radix_tile=0, handler=0):
-    return Params(P, s, investigator, fanin, merge_tile, radix_tile, handler, 0)
+def _params(P, s, investigator, fanin, merge_tile, radix_tile=0, handler=0, presorted=0):
+    return Params(P, s, investigator, fanin, merge_tile, radix_tile, handler, presorted, 0)
 
 
 def _alloc_parts(B, P, kdt, device, want_send, want_cuts):
@@ -163,7 +164,7 @@ def _run(fn, args_before_ws, ws: Workspace | None, device):
 
 
 def sort_batch(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torch.Tensor | None = None,
-               s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0, handler: int = 0,
+               s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0, handler: int = 0, presorted: int = 0,
                keys_out=None, vals_out=None, want_send=False, want_cuts=False,
                workspace: Workspace | None = None, index_values: bool = False) -> SortResult:
     """lbsort_sort_batch: seg_offsets is a device tensor of B+1 offsets (int64/uint64).
@@ -177,7 +178,7 @@ def sort_batch(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torc
         vals_out = torch.empty(n, dtype=torch.uint32, device=keys.device)
     vt = VAL_U32 if vals is not None else (VAL_INDEX if index_values else NOVAL)
     parts, offs, counts, spl, send, cuts = _alloc_parts(B, P, keys.dtype, keys.device, want_send, want_cuts)
-    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile, handler)
+    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile, handler, presorted)
     args = (kc, vt, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
             _ptr(seg_offsets), B, n, ctypes.byref(prm), ctypes.byref(parts))
     buf = _run(lib.lbsort_sort_batch, args, workspace, keys.device)
@@ -186,20 +187,21 @@ def sort_batch(keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torc
 
 def sort_keys(keys: torch.Tensor, P: int, s: int = 0, investigator: int = INV_COUNT, fanin: int = 0,
               merge_tile: int = 0, keys_out=None, want_send=False, want_cuts=False,
-              workspace: Workspace | None = None, radix_tile: int = 0, handler: int = 0) -> SortResult:
+              workspace: Workspace | None = None, radix_tile: int = 0, handler: int = 0,
+              presorted: int = 0) -> SortResult:
     """lbsort_sort_keys on one array."""
     lib = load()
     kc = key_code(keys.dtype)
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
     parts, offs, counts, spl, send, cuts = _alloc_parts(1, P, keys.dtype, keys.device, want_send, want_cuts)
-    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile, handler)
+    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile, handler, presorted)
     args = (kc, _ptr(keys), _ptr(keys_out), keys.numel(), ctypes.byref(prm), ctypes.byref(parts))
     buf = _run(lib.lbsort_sort_keys, args, workspace, keys.device)
     return SortResult(keys_out, None, offs, counts, spl, send, cuts, buf)
 
 
 def sort_pairs(keys: torch.Tensor, vals: torch.Tensor | None, P: int, s: int = 0, investigator: int = INV_COUNT,
-               fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0, handler: int = 0, keys_out=None, vals_out=None, want_send=False,
+               fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0, handler: int = 0, presorted: int = 0, keys_out=None, vals_out=None, want_send=False,
                want_cuts=False, workspace: Workspace | None = None) -> SortResult:
     """lbsort_sort_pairs on one array of keys with uint32 values.  vals=None
     sorts with LBSORT_VAL_INDEX: vals_out receives every key's input position."""
@@ -211,7 +213,7 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor | None, P: int, s: int = 0
     if vals_out is None:
         vals_out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
     parts, offs, counts, spl, send, cuts = _alloc_parts(1, P, keys.dtype, keys.device, want_send, want_cuts)
-    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile, handler)
+    prm = _params(P, s, investigator, fanin, merge_tile, radix_tile, handler, presorted)
     args = (kc, VAL_U32 if vals is not None else VAL_INDEX, _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out),
             keys.numel(), ctypes.byref(prm), ctypes.byref(parts))
     buf = _run(lib.lbsort_sort_pairs, args, workspace, keys.device)
@@ -286,18 +288,20 @@ def autotune(key_type: int, val_type: int, P: int, total_n: int = 0, B: int = 1,
     out = Params()
     _check(lib.lbsort_autotune(key_type, val_type, _ptr(keys), _ptr(vals), _ptr(seg_offsets), B, total_n, P,
                                cache_path.encode() if cache_path else None, ctypes.byref(out)))
-    return {"fanin": out.fanin, "merge_tile": out.merge_tile, "radix_tile": out.radix_tile, "handler": out.handler}
+    return {"fanin": out.fanin, "merge_tile": out.merge_tile, "radix_tile": out.radix_tile, "handler": out.handler,
+            "presorted": out.presorted}
 
 
 def resolve_params(key_type: int, val_type: int, P: int, total_n: int, B: int = 1, s: int = 0,
                    investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0,
-                   handler: int = 0) -> dict:
+                   handler: int = 0, presorted: int = 0) -> dict:
     """lbsort_resolve_params: the settings a call of this shape would use."""
-    prm = Params(P, s, investigator, fanin, merge_tile, radix_tile, handler, 0)
+    prm = Params(P, s, investigator, fanin, merge_tile, radix_tile, handler, presorted, 0)
     out = Params()
     _check(load().lbsort_resolve_params(key_type, val_type, B, total_n, ctypes.byref(prm), ctypes.byref(out)))
     return {"P": out.P, "s": out.s, "investigator": out.investigator, "fanin": out.fanin,
-            "merge_tile": out.merge_tile, "radix_tile": out.radix_tile, "handler": out.handler}
+            "merge_tile": out.merge_tile, "radix_tile": out.radix_tile, "handler": out.handler,
+            "presorted": out.presorted}
 
 
 def load_tuning(cache_path: str):
@@ -316,7 +320,7 @@ class BatchPlan:
     """
 
     def __init__(self, keys: torch.Tensor, seg_offsets: torch.Tensor, P: int, vals: torch.Tensor | None = None,
-                 s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0, handler: int = 0,
+                 s: int = 0, investigator: int = INV_COUNT, fanin: int = 0, merge_tile: int = 0, radix_tile: int = 0, handler: int = 0, presorted: int = 0,
                  keys_out=None, vals_out=None):
         lib = load()
         self.keys, self.vals, self.seg = keys, vals, seg_offsets
@@ -326,7 +330,7 @@ class BatchPlan:
         self.vals_out = (torch.empty_like(vals) if vals_out is None else vals_out) if vals is not None else None
         (self._parts, self.part_offsets, self.part_counts, self.splitters, _, _) = _alloc_parts(
             self.B, P, keys.dtype, keys.device, False, False)
-        self._prm = _params(P, s, investigator, fanin, merge_tile, radix_tile, handler)
+        self._prm = _params(P, s, investigator, fanin, merge_tile, radix_tile, handler, presorted)
         self._args = (key_code(keys.dtype), VAL_U32 if vals is not None else NOVAL, _ptr(keys), _ptr(vals),
                       _ptr(self.keys_out), _ptr(self.vals_out), _ptr(seg_offsets), self.B, keys.numel(),
                       ctypes.byref(self._prm), ctypes.byref(self._parts))

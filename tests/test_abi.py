@@ -41,7 +41,7 @@ def test_status_strings(lib):
 
 def _size(key_type=L.U64, P=8, n=1000, **kw):
     prm = L.Params(P, kw.get("s", 0), kw.get("inv", 0), kw.get("fanin", 0), kw.get("tile", 0), kw.get("rtile", 0),
-                   kw.get("handler", 0), kw.get("reserved", 0))
+                   kw.get("handler", 0), kw.get("presorted", 0), kw.get("reserved", 0))
     parts = L.Parts(1, 0, 0, 0, 0)
     need = ctypes.c_size_t(0)
     rc = L.load().lbsort_sort_keys(key_type, None, None, n, ctypes.byref(prm), ctypes.byref(parts), None,
@@ -67,8 +67,10 @@ def test_workspace_query_and_growth(lib):
     (dict(tile=1000), L.ERR_INVALID_ARG),
     (dict(rtile=1000), L.ERR_INVALID_ARG),
     (dict(rtile=2048), L.ERR_INVALID_ARG),
+    (dict(rtile=16384), L.ERR_INVALID_ARG),                  # 64-bit keys: no 16384-key tiles
     (dict(reserved=1), L.ERR_INVALID_ARG),
     (dict(handler=3), L.ERR_INVALID_ARG),
+    (dict(presorted=3), L.ERR_INVALID_ARG),
     (dict(handler=2, P=65), L.ERR_UNSUPPORTED),
     (dict(handler=2, P=64, fanin=16), L.ERR_INVALID_ARG),
     (dict(handler=2, P=64, tile=1024), L.ERR_INVALID_ARG),
@@ -154,7 +156,7 @@ def test_resolve_params_defaults_and_explicit(lib):
     8192; s = the paper's budget.  Explicit settings pass through."""
     r = L.resolve_params(L.U64, L.VAL_U32, 64, 1 << 28)
     assert r == {"P": 64, "s": 512, "investigator": 0, "fanin": 8, "merge_tile": 2048, "radix_tile": 8192,
-                 "handler": L.HANDLER_PASSES}
+                 "handler": L.HANDLER_PASSES, "presorted": L.PRESORTED_DETECT}
     r = L.resolve_params(L.U64, L.VAL_U32, 37, 1 << 20, handler=L.HANDLER_ONE_PASS)
     assert r["handler"] == L.HANDLER_ONE_PASS and r["fanin"] == 64 and r["merge_tile"] == 4096
     assert L.resolve_params(L.U64, L.NOVAL, 128, 1 << 20)["handler"] == L.HANDLER_PASSES
@@ -164,7 +166,8 @@ def test_resolve_params_defaults_and_explicit(lib):
     r = L.resolve_params(L.F64, L.VAL_INDEX, 10, 10 ** 6, s=7, investigator=2, fanin=4, merge_tile=1024,
                          radix_tile=4096)
     assert r == {"P": 10, "s": 7, "investigator": 2, "fanin": 4, "merge_tile": 1024, "radix_tile": 4096,
-                 "handler": L.HANDLER_PASSES}
+                 "handler": L.HANDLER_PASSES, "presorted": L.PRESORTED_DETECT}
+    assert L.resolve_params(L.U64, L.NOVAL, 10, 1000, presorted=L.PRESORTED_IGNORE)["presorted"] == L.PRESORTED_IGNORE
     r = L.resolve_params(L.U64, L.NOVAL, 10, 10 ** 6, handler=L.HANDLER_ONE_PASS, merge_tile=2048)
     assert r["handler"] == L.HANDLER_ONE_PASS and r["fanin"] == 16 and r["merge_tile"] == 2048
     with pytest.raises(L.LbsortError):
@@ -174,13 +177,22 @@ def test_resolve_params_defaults_and_explicit(lib):
 def test_radix_tile_sizes_the_workspace(lib):
     """Smaller radix tiles need more look-back status words."""
     def need(rt):
-        prm = L.Params(8, 0, 0, 0, 0, rt, 0, 0)
+        prm = L.Params(8, 0, 0, 0, 0, rt, 0, 0, 0)
         parts = L.Parts(1, 0, 0, 0, 0)
         n = ctypes.c_size_t(0)
         assert lib.lbsort_sort_keys(L.U64, None, None, 1 << 22, ctypes.byref(prm), ctypes.byref(parts), None,
                                     ctypes.byref(n), None) == 0
         return n.value
     assert need(4096) > need(8192) == need(0)
+    # 32-bit keys also take tiles of 16384 keys (fewer status words)
+    def need32(rt):
+        prm = L.Params(8, 0, 0, 0, 0, rt, 0, 0, 0)
+        parts = L.Parts(1, 0, 0, 0, 0)
+        n = ctypes.c_size_t(0)
+        assert lib.lbsort_sort_keys(L.F32, None, None, 1 << 22, ctypes.byref(prm), ctypes.byref(parts), None,
+                                    ctypes.byref(n), None) == 0
+        return n.value
+    assert need32(8192) > need32(16384)
 
 
 def test_autotune_argument_checks(lib):

@@ -281,3 +281,24 @@ def test_radix_tiles_agree_on_every_local_sort_path(ws, monkeypatch):
         for rtile in (4096, 8192):
             r = run_gpu(keys, vals, 16, 0, ws=ws, rtile=rtile)
             assert np.array_equal(ka, to_host(r.keys)) and np.array_equal(va, to_host(r.vals)), (lsd, rtile)
+
+
+def test_radix_tile_16384_for_32bit_keys(ws):
+    """Tiles of 16384 keys (32-bit keys only): pairs and keys, blocks just
+    above one and several tiles, a batch of uneven instances."""
+    n = 1_234_567
+    check_case(datagen.uniform_keys(n, seed=5, dtype=np.uint32), datagen.index_values(n), 8, 0, ws=ws, rtile=16384)
+    check_case(datagen.normal_u32(n, seed=6), None, 13, 0, ws=ws, rtile=16384)
+    for n, P in ((16_383, 1), (16_385, 1), (3 * 16_384 + 5, 1), (100_003, 3)):
+        k = datagen.uniform_keys(n, seed=n + P, dtype=np.uint32)
+        check_case(k, datagen.index_values(n), P, 4, ws=ws, rtile=16384)
+    sizes = [0, 5, 4097, 16_385, 70_000, 1, 250_000]
+    keys = np.concatenate([datagen.uniform_keys(m, seed=300 + i, dtype=np.uint32) for i, m in enumerate(sizes)])
+    vals = np.concatenate([np.arange(m, dtype=np.uint32) for m in sizes])
+    seg = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    r = L.sort_batch(to_dev(keys), to_dev(seg), 8, vals=to_dev(vals), s=16, want_send=True, want_cuts=True,
+                     radix_tile=16384)
+    L.check(r.workspace)
+    for b in range(len(sizes)):
+        a, e = int(seg[b]), int(seg[b + 1])
+        compare(r, O.sample_sort(keys[a:e], vals[a:e], 8, 16), 8, b=b, seg=(a, e))
