@@ -97,8 +97,8 @@ __global__ __launch_bounds__(1024) void k_merge_plan(Plan p, Level L) {
     __syncthreads();
   }
   if (tid == 0) p.mtile[L.NG] = (u32)carry;
-  // Group descriptors, and the owner group of every boundary slot, so that a
-  // boundary's wave starts with independent loads only.
+  // Group descriptors, so that a boundary's wave starts with independent
+  // loads only (the owner group of each boundary slot: k_slot_grp).
   for (u32 g = tid; g < L.NG; g += 1024) {
     u64 off, len;
     group_info(p, L, g, off, len);
@@ -111,11 +111,19 @@ __global__ __launch_bounds__(1024) void k_merge_plan(Plan p, Level L) {
       p.grp_run[((u64)g * p.F + r) * 2 + 1] = rl;
     }
   }
-  __syncthreads();
-  for (u32 g = tid; g < L.NG; g += 1024) {
-    const u32 a = p.mtile[g] + g, e = p.mtile[g + 1] + g + 1;
-    for (u32 q = a; q < e; ++q) p.slot_grp[q] = g;
+}
+
+// The owner group of every boundary slot (group g owns slots [mtile[g] + g,
+// mtile[g+1] + g + 1)): one thread per slot, a binary search over the groups.
+__global__ __launch_bounds__(256) void k_slot_grp(Plan p, Level L, u32 slots) {
+  const u32 q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= slots || q >= p.mtile[L.NG] + L.NG) return;
+  u32 lo = 0, hi = L.NG;  // the last g with mtile[g] + g <= q
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if (p.mtile[mid] + mid <= q) lo = mid; else hi = mid;
   }
+  p.slot_grp[q] = lo;
 }
 
 // One wave per tile boundary.  Group g owns boundary slots
@@ -352,6 +360,7 @@ static void run_level(const Plan& p, const Level& L, const K* src, const u32* sr
   constexpr int M = F * F / 64 > 1 ? F * F / 64 : 1;
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_merge_plan, dim3(1), dim3(1024), 0, s, p, L); prof_end(pe_, "merge_plan", s); }
   const u64 slots = max_tiles + L.NG + 1;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_slot_grp, dim3((u32)((slots + 255) / 256)), dim3(256), 0, s, p, L, (u32)slots); prof_end(pe_, "slot_grp", s); }
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M, false>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition_coarse", s); }
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M, true>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition_fine", s); }
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_merge<K, HASV, F, TM>), dim3((u32)max_tiles), dim3(256), 0, s, p, L, src, srcv, dst,
