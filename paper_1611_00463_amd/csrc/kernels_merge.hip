@@ -201,9 +201,12 @@ __device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* 
   u32 a1 = 0, b1 = 0, ia = 0, ib = 0;
   K ka = 0, kb = 0;
   auto start = [&](u32 q) {
+    // the pair holding output q: the last pair start so[2wj] <= q (a binary
+    // search over the F / 2w pair starts)
     u32 j = 0;
 #pragma unroll
-    for (int x = 2 * w; x < F; x += 2 * w) j += (q >= so[x]) ? 1u : 0u;
+    for (int st = F / (4 * w); st >= 1; st >>= 1)
+      if (so[2 * w * (j + st)] <= q) j += st;
     const u32 a0 = so[2 * j * w];
     a1 = so[min((u32)((2 * j + 1) * w), (u32)F)];
     b1 = so[min((u32)((2 * j + 2) * w), (u32)F)];
@@ -280,17 +283,25 @@ __global__ __launch_bounds__(NT) void k_merge(Plan p, Level L, const K* __restri
   const u32 n = s_so[F];
   {
     // source positions first, then every load at once (past n: element 0,
-    // always present when a tile exists), then the LDS stores
+    // always present when a tile exists), then the LDS stores; the run of
+    // each element is the last run start <= its slot (a binary search over
+    // the F starts, the IT searches interleaved)
     u64 e[IT];
-    u32 r = 0;
+    u32 r[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) r[i] = 0;
+#pragma unroll
+    for (int st = F / 2; st >= 1; st >>= 1) {
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const u32 q = tid + (u32)i * NT;
+        if (s_so[r[i] + st] <= q) r[i] += st;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const u32 q = tid + (u32)i * NT;
-      e[i] = 0;
-      if (q < n) {
-        while (r + 1 < (u32)F && q >= s_so[r + 1]) ++r;
-        e[i] = s_roff[r] + (q - s_so[r]);
-      }
+      e[i] = q < n ? s_roff[r[i]] + (q - s_so[r[i]]) : 0;
     }
     K kv[IT];
     u32 vv[HASV ? IT : 1];
