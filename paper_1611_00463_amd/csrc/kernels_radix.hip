@@ -483,10 +483,13 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
   static_assert(NT >= RADIX, "one thread per digit");
   // LDS: 16-bit per-wave digit counters (they end up holding the tile-local
   // start of each wave's run of a digit), 32-bit block-relative write bases,
-  // and the tile staged in digit order: keys in s_stage, values in s_vstage,
-  // so both go out in one pass (about 105 KB for 64-bit keys with values: one
-  // workgroup per compute unit).  One struct, small fields first, so that
+  // and the tile staged in digit order.  With 8 items per thread keys and
+  // values are staged together; with 16 (SPLITV) the values are loaded and
+  // staged after the keys have gone out, in the same buffer, so that neither
+  // the registers nor the LDS hold both (two 8192-key workgroups per compute
+  // unit stay within 80 KB each).  One struct, small fields first, so that
   // they sit at addresses the LDS instructions' immediate offsets reach.
+  constexpr bool SPLITV = HASV && ITEMS > 8;
   struct Smem {
     u32 ticket;    // current ticket
     TileDesc td;   // its tile
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
     u32 gbase[RADIX];
     uint16_t wc[NWV][RADIX];
     K stage[TILE];
-    u32 vstage[HASV ? TILE : 1];
+    u32 vstage[HASV && !SPLITV ? TILE : 1];
   };
   __shared__ Smem sm;
   auto& s_scan = sm.scan;
@@ -567,18 +570,19 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
       if (tid < RADIX) hv = hrow[tid];
       const u32 wbase = w * WI;
 
+      // (SPLITV: the values are loaded after the keys have gone out)
       K keys[ITEMS];
-      u32 vals[HASV ? ITEMS : 1];
-      if (!HASV || srcv != nullptr) {
+      u32 vals[HASV && !SPLITV ? ITEMS : 1];
+      if (!HASV || SPLITV || srcv != nullptr) {
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
           const u32 idx = wbase + j * 64 + lane;
           if (idx < tile_n) {
             keys[j] = src[tbase + idx];
-            if (HASV) vals[j] = srcv[tbase + idx];
+            if (HASV && !SPLITV) vals[j] = srcv[tbase + idx];
           } else {
             keys[j] = 0;
-            if (HASV) vals[j] = 0;
+            if (HASV && !SPLITV) vals[j] = 0;
           }
         }
       } else {
@@ -590,7 +594,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
         for (int j = 0; j < ITEMS; ++j) {
           const u32 idx = wbase + j * 64 + lane;
           keys[j] = idx < tile_n ? src[tbase + idx] : (K)0;
-          if (HASV) vals[j] = (u32)(vgen + idx);
+          if (HASV && !SPLITV) vals[j] = (u32)(vgen + idx);
         }
       }
       if ((kx_top | kx_fm) != 0) {
@@ -659,7 +663,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
         rank[j] += s_wc[w][(u32)(keys[j] >> shift) & (RADIX - 1)];  // rank[] now holds the staged position
         if (wbase + j * 64 + lane < tile_n) {
           s_stage[rank[j]] = keys[j];
-          if (HASV) s_vstage[rank[j]] = vals[j];
+          if (HASV && !SPLITV) s_vstage[rank[j]] = vals[j];
         }
       }
       u64 excl = 0;
@@ -706,11 +710,60 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
       __syncthreads();
       K* const dblk = dst + bstart;
       u32* const vblk = HASV ? dstv + bstart : nullptr;
-      for (u32 i = tid; i < tile_n; i += NT) {
-        const K k = s_stage[i];
-        const u32 o = s_gbase[(u32)(k >> shift) & (RADIX - 1)] + i;
-        dblk[o] = k;
-        if (HASV) vblk[o] = s_vstage[i];
+      // Write-out: staged position i = j * NT + tid goes to its digit's base
+      // + i.  The LDS reads of a chunk of CH items first, then its stores, so
+      // that the LDS latency is paid once per chunk rather than once per item.
+      constexpr int CH = ITEMS < 8 ? ITEMS : 8;
+      u32 oo[SPLITV ? ITEMS : 1];
+#pragma unroll
+      for (int c = 0; c < ITEMS; c += CH) {
+        K ok[CH];
+        u32 oc[CH];
+        u32 ov[HASV && !SPLITV ? CH : 1];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const u32 i = (u32)(c + j) * NT + tid;
+          ok[j] = i < tile_n ? s_stage[i] : (K)0;
+          if (HASV && !SPLITV) ov[j] = i < tile_n ? s_vstage[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          oc[j] = s_gbase[(u32)(ok[j] >> shift) & (RADIX - 1)] + (u32)(c + j) * NT + tid;
+          if (SPLITV) oo[c + j] = oc[j];
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+          if ((u32)(c + j) * NT + tid < tile_n) {
+            dblk[oc[j]] = ok[j];
+            if (HASV && !SPLITV) vblk[oc[j]] = ov[j];
+          }
+      }
+      if (SPLITV) {
+        // the values, through the same buffer once every key has been read
+        // from it; staged position and destination are the keys'
+        u32* const s_vs = reinterpret_cast<u32*>(&s_stage[0]);
+        u32 vv[ITEMS];
+        if (srcv != nullptr) {
+#pragma unroll
+          for (int j = 0; j < ITEMS; ++j) {
+            const u32 idx = wbase + j * 64 + lane;
+            vv[j] = idx < tile_n ? srcv[tbase + idx] : 0u;
+          }
+        } else {
+          const u64 vgen = tbase - p.seg[blk / p.P];
+#pragma unroll
+          for (int j = 0; j < ITEMS; ++j) vv[j] = (u32)(vgen + wbase + j * 64 + lane);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+          if (wbase + j * 64 + lane < tile_n) s_vs[rank[j]] = vv[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+          const u32 i = (u32)j * NT + tid;
+          if (i < tile_n) vblk[oo[j]] = s_vs[i];
+        }
       }
     }
   }
@@ -1434,12 +1487,16 @@ void launch_small_sort(const Plan& p, const K* src, const u32* srcv, K* dst, u32
 template <typename K, bool HASV>
 void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, u32 pass, hipStream_t s) {
   if (p.max_tiles == 0) return;
-  // Persistent grid: tiles of 8192 keys take one 1024-thread workgroup per
-  // compute unit (8 keys per thread; about 105 KB of LDS for 64-bit keys with
-  // values), tiles of 4096 keys two 512-thread workgroups, and tiles of 16384
-  // 32-bit keys one 1024-thread workgroup with 16 keys per thread (about
-  // 137 KB with values); a multiple of the queue count.
-  const u32 NT = p.rtile == RTILE_HUGE ? 1024 : p.rtile / 8;
+  // Persistent grid: tiles of 4096 keys take 512-thread workgroups with 8
+  // keys per thread, tiles of 8192 keys 512-thread workgroups with 16 keys
+  // per thread (two workgroups per compute unit: at most 80 KB of LDS each),
+  // except 64-bit keys with values, whose tiles of 8192 take one 1024-thread
+  // workgroup per compute unit with 8 keys and 8 values per thread (measured
+  // faster than loading the values in a second phase), and tiles of 16384
+  // 32-bit keys take one 1024-thread workgroup with 16 keys per thread; a
+  // multiple of the queue count.
+  constexpr bool WIDE_PAIRS = sizeof(K) == 8 && HASV;
+  const u32 NT = p.rtile == RTILE_HUGE || (WIDE_PAIRS && p.rtile == RTILE_LARGE) ? 1024 : 512;
   u32 grid = p.persist_wgs * 256 / NT;
   grid = grid < p.max_tiles ? grid : p.max_tiles;
   grid = (grid + p.nq - 1) / p.nq * p.nq;
@@ -1463,12 +1520,19 @@ void launch_onesweep(const Plan& p, const K* src, const u32* srcv, K* dst, u32* 
     else
       hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_SMALL / 8, 8, 2, false>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
                          dst, dstv, pass);
-  } else {
+  } else if constexpr (WIDE_PAIRS) {
     if (p.only)
       hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_LARGE / 8, 8, 1, true>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
                          dst, dstv, pass);
     else
       hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_LARGE / 8, 8, 1, false>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
+                         dst, dstv, pass);
+  } else {
+    if (p.only)
+      hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_LARGE / 16, 16, 4, true>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
+                         dst, dstv, pass);
+    else
+      hipLaunchKernelGGL((k_onesweep<K, HASV, RTILE_LARGE / 16, 16, 4, false>), dim3(grid), dim3(NT), 0, s, p, src, srcv,
                          dst, dstv, pass);
   }
   prof_end(pe_, p.only ? "onesweep_fallback" : "onesweep", s);

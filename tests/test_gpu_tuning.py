@@ -24,7 +24,7 @@ def test_autotune_on_a_batch_and_use_it(tmp_path):
     path = str(tmp_path / "tune.json")
     before = L.resolve_params(L.U32, L.VAL_U32, P, total, B=B)
     chosen = L.autotune(L.U32, L.VAL_U32, P, keys=keys, vals=vals, seg_offsets=seg, cache_path=path)
-    assert chosen["radix_tile"] in (4096, 8192)
+    assert chosen["radix_tile"] in (4096, 8192, 16384)  # 16384 only for 32-bit keys
     assert chosen["fanin"] in (2, 4, 8) and chosen["merge_tile"] in (1024, 2048, 4096)
     # the cache file holds the entry, keyed by the device architecture
     entries = json.load(open(path))["entries"]
