@@ -374,7 +374,9 @@ static void run_level(const Plan& p, const Level& L, const K* src, const u32* sr
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_slot_grp, dim3((u32)((slots + 255) / 256)), dim3(256), 0, s, p, L, (u32)slots); prof_end(pe_, "slot_grp", s); }
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M, false>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition_coarse", s); }
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_partition<K, F, M, true>), dim3((u32)((slots + 3) / 4)), dim3(256), 0, s, p, L, src); prof_end(pe_, "partition_fine", s); }
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_merge<K, HASV, F, TM>), dim3((u32)max_tiles), dim3(256), 0, s, p, L, src, srcv, dst,
+  // eight outputs per thread for tiles of 2048 and 4096, four for 1024
+  constexpr int NT = TM >= 2048 ? TM / 8 : 256;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL((k_merge<K, HASV, F, TM, NT>), dim3((u32)max_tiles), dim3(NT), 0, s, p, L, src, srcv, dst,
                      dstv); prof_end(pe_, "merge", s); }
 }
 
