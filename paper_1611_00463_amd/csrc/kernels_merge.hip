@@ -193,24 +193,25 @@ __device__ inline u32 pad8(u32 q) { return q + (q >> 3); }
 
 // One thread's IT consecutive outputs [q0, q0 + IT) of a merge level where
 // lists of `w` segments are merged pairwise (A = [a0, a1), B = [a1, b1), ties to
-// A).  The outputs are produced into registers; a thread whose range runs past
-// the end of its pair starts over in the next pair (merge-path search again).
-template <typename K, bool IDX, int IT, int F, bool FULL>
-__device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* so, int w, u32 q0, u32 n,
+// A).  The outputs are produced into registers.  Only the first output needs
+// a merge-path search: a thread whose range runs past the end of its pair
+// goes on with the next pair, whose first output is that pair's start with
+// nothing taken from either side yet.
+template <typename K, bool IDX, int IT, int F>
+__device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* so, u32 w, u32 q0, u32 n,
                                     K (&ok)[IT], uint16_t (&oi)[IT]) {
-  u32 a1 = 0, b1 = 0, ia = 0, ib = 0;
-  K ka = 0, kb = 0;
-  auto start = [&](u32 q) {
-    // the pair holding output q: the last pair start so[2wj] <= q (a binary
-    // search over the F / 2w pair starts)
-    u32 j = 0;
-#pragma unroll
-    for (int st = F / (4 * w); st >= 1; st >>= 1)
-      if (so[2 * w * (j + st)] <= q) j += st;
-    const u32 a0 = so[2 * j * w];
-    a1 = so[min((u32)((2 * j + 1) * w), (u32)F)];
-    b1 = so[min((u32)((2 * j + 2) * w), (u32)F)];
-    const u32 la = a1 - a0, lb = b1 - a1, diag = q - a0;
+  if (q0 >= n) return;
+  // the pair holding output q0: the last pair start so[2wj] <= q0 (a binary
+  // search over the F / 2w pair starts)
+  u32 j = 0;
+  for (u32 st = F / (4 * w); st >= 1; st >>= 1)
+    if (so[2 * w * (j + st)] <= q0) j += st;
+  const u32 a0 = so[2 * j * w];
+  u32 a1 = so[min((2 * j + 1) * w, (u32)F)];
+  u32 b1 = so[min((2 * j + 2) * w, (u32)F)];
+  u32 ia, ib;
+  {
+    const u32 la = a1 - a0, lb = b1 - a1, diag = q0 - a0;
     u32 lo = diag > lb ? diag - lb : 0, hi = diag < la ? diag : la;
     while (lo < hi) {
       const u32 mid = (lo + hi) >> 1;
@@ -218,16 +219,24 @@ __device__ inline void merge_thread(const K* ck, const uint16_t* ci, const u32* 
     }
     ia = a0 + lo;
     ib = a1 + diag - lo;
-    ka = ia < a1 ? ck[pad8(ia)] : (K)0;
-    kb = ib < b1 ? ck[pad8(ib)] : (K)0;
-  };
-  // FULL: the tile holds TM outputs, so every thread's IT outputs exist
-  if (FULL || q0 < n) start(q0);
+  }
+  K ka = ia < a1 ? ck[pad8(ia)] : (K)0;
+  K kb = ib < b1 ? ck[pad8(ib)] : (K)0;
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const u32 q = q0 + i;
-    if (FULL || q < n) {
-      if (q == b1) start(q);
+    if (q < n) {
+      // past the end of the pair (possibly several empty ones): the next
+      // pair; it ends at so[F] = n > q at the latest
+      while (q == b1) {
+        ++j;
+        ia = b1;
+        a1 = so[min((2 * j + 1) * w, (u32)F)];
+        b1 = so[min((2 * j + 2) * w, (u32)F)];
+        ib = a1;
+        ka = ia < a1 ? ck[pad8(ia)] : (K)0;
+        kb = ib < b1 ? ck[pad8(ib)] : (K)0;
+      }
       // branch-free step: emit the smaller front, reload only the side consumed
       const bool takeA = ib >= b1 || (ia < a1 && ka <= kb);
       const u32 from = takeA ? ia : ib;
@@ -324,14 +333,14 @@ __global__ __launch_bounds__(NT) void k_merge(Plan p, Level L, const K* __restri
   }
   __syncthreads();
   const u32 q0 = tid * IT;
-#pragma unroll
-  for (int w = 1; w < F; w <<= 1) {
+  // up to four levels unrolled; a 32- or 64-way tile runs one copy of the
+  // level's code (the levels differ in w only), so that the kernel stays
+  // small in the instruction cache
+#pragma unroll(F <= 16 ? 4 : 1)
+  for (u32 w = 1; w < (u32)F; w <<= 1) {
     K ok[IT];
     uint16_t oi[IT];
-    if (n == (u32)TM)
-      merge_thread<K, HASV, IT, F, true>(s_k, s_i, s_so, w, q0, n, ok, oi);
-    else
-      merge_thread<K, HASV, IT, F, false>(s_k, s_i, s_so, w, q0, n, ok, oi);
+    merge_thread<K, HASV, IT, F>(s_k, s_i, s_so, w, q0, n, ok, oi);
     __syncthreads();
     // q0 is a multiple of IT (4, 8 or 16) and (q0 mod 8) + i < 8 whenever
     // i < 8, so pad8(q0 + i) = pad8(q0) + i + i / 8
