@@ -60,20 +60,30 @@ __device__ inline void run_info(const Plan& p, const Level& L, u32 gidx, u32 r, 
   if (len > lim - off) len = lim - off;
 }
 
-// Tile counts of every group of this pass, prefix-summed (single workgroup).
+// Tile counts of every group of this pass, prefix-summed (single workgroup;
+// each thread takes GPT consecutive groups per round, their loads issued
+// together).
 __global__ __launch_bounds__(1024) void k_merge_plan(Plan p, Level L) {
+  constexpr u32 GPT = 8;
   __shared__ u64 s_w[16];
   const u32 tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   u64 carry = 0;
-  for (u32 base = 0; base < L.NG; base += 1024) {
-    const u32 g = base + tid;
-    u64 nt = 0;
-    if (g < L.NG) {
-      u64 off, len;
-      group_info(p, L, g, off, len);
-      nt = (len + p.TM - 1) / p.TM;
+  for (u32 base = 0; base < L.NG; base += 1024 * GPT) {
+    const u32 g0 = base + tid * GPT;
+    u64 nt[GPT];
+#pragma unroll
+    for (u32 i = 0; i < GPT; ++i) {
+      nt[i] = 0;
+      if (g0 + i < L.NG) {
+        u64 off, len;
+        group_info(p, L, g0 + i, off, len);
+        nt[i] = (len + p.TM - 1) / p.TM;
+      }
     }
-    u64 x = nt;
+    u64 mine = 0;
+#pragma unroll
+    for (u32 i = 0; i < GPT; ++i) mine += nt[i];
+    u64 x = mine;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       u64 y = __shfl_up(x, o);
@@ -91,32 +101,37 @@ __global__ __launch_bounds__(1024) void k_merge_plan(Plan p, Level L) {
       if (lane < 16) s_w[lane] = t;
     }
     __syncthreads();
-    const u64 ex = carry + (w ? s_w[w - 1] : 0) + x - nt;
-    if (g < L.NG) p.mtile[g] = (u32)ex;
+    u64 ex = carry + (w ? s_w[w - 1] : 0) + x - mine;
+#pragma unroll
+    for (u32 i = 0; i < GPT; ++i) {
+      if (g0 + i < L.NG) p.mtile[g0 + i] = (u32)ex;
+      ex += nt[i];
+    }
     carry += s_w[15];
     __syncthreads();
   }
   if (tid == 0) p.mtile[L.NG] = (u32)carry;
-  // Group descriptors, so that a boundary's wave starts with independent
-  // loads only (the owner group of each boundary slot: k_slot_grp).
-  for (u32 g = tid; g < L.NG; g += 1024) {
-    u64 off, len;
-    group_info(p, L, g, off, len);
-    p.grp_out[2 * (u64)g] = off;
-    p.grp_out[2 * (u64)g + 1] = len;
-    for (u32 r = 0; r < p.F; ++r) {
-      u64 ro, rl;
-      run_info(p, L, g, r, ro, rl);
-      p.grp_run[((u64)g * p.F + r) * 2] = ro;
-      p.grp_run[((u64)g * p.F + r) * 2 + 1] = rl;
-    }
-  }
 }
 
 // The owner group of every boundary slot (group g owns slots [mtile[g] + g,
 // mtile[g+1] + g + 1)): one thread per slot, a binary search over the groups.
+// Also the group descriptors, one thread per (group, run), so that a
+// boundary's wave starts with independent loads only.
 __global__ __launch_bounds__(256) void k_slot_grp(Plan p, Level L, u32 slots) {
   const u32 q = blockIdx.x * 256 + threadIdx.x;
+  for (u64 x = q; x < (u64)L.NG * p.F; x += (u64)gridDim.x * 256) {
+    const u32 g = (u32)(x / p.F), r = (u32)(x % p.F);
+    u64 ro, rl;
+    run_info(p, L, g, r, ro, rl);
+    p.grp_run[2 * x] = ro;
+    p.grp_run[2 * x + 1] = rl;
+    if (r == 0) {
+      u64 off, len;
+      group_info(p, L, g, off, len);
+      p.grp_out[2 * (u64)g] = off;
+      p.grp_out[2 * (u64)g + 1] = len;
+    }
+  }
   if (q >= slots || q >= p.mtile[L.NG] + L.NG) return;
   u32 lo = 0, hi = L.NG;  // the last g with mtile[g] + g <= q
   while (hi - lo > 1) {
