@@ -69,42 +69,63 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
   __syncthreads();
   const bool bad = s_bad != 0;
   if (bad && tid == 0) set_error(p.counters, E_SEG);
+  // BPT consecutive blocks per thread and round, their loads issued together
+  constexpr u32 BPT = 8;
   u64 carry_t = 0, carry_s = 0, carry_m = 0, carry_l = 0;
-  for (u32 base = 0; base < p.NB; base += 1024) {
-    const u32 idx = base + tid;
-    u64 n = 0, bs = 0;
-    if (idx < p.NB) {
-      const u32 b = idx / p.P, i = idx % p.P;
-      if (!bad) {
-        bs = block_begin(p.seg, b, i, p.P);
-        n = block_begin(p.seg, b, i + 1, p.P) - bs;
+  for (u32 base = 0; base < p.NB; base += 1024 * BPT) {
+    const u32 i0 = base + tid * BPT;
+    u64 tiles[BPT], smp[BPT];
+    bool small[BPT];
+    u64 st = 0, ss = 0, sl = 0, sm = 0;
+#pragma unroll
+    for (u32 j = 0; j < BPT; ++j) {
+      const u32 idx = i0 + j;
+      u64 n = 0, bs = 0;
+      if (idx < p.NB) {
+        const u32 b = idx / p.P, i = idx % p.P;
+        if (!bad) {
+          bs = block_begin(p.seg, b, i, p.P);
+          n = block_begin(p.seg, b, i + 1, p.P) - bs;
+        }
+        if (n >= (1ull << 32)) {
+          set_error(p.counters, E_RANGE);
+          n = 0;
+        }
+        p.blk_start[idx] = bs;
       }
-      if (n >= (1ull << 32)) {
-        set_error(p.counters, E_RANGE);
-        n = 0;
-      }
-      p.blk_start[idx] = bs;
+      // with a filter, only the listed large blocks are planned (small blocks
+      // and sample offsets are unaffected by it)
+      const bool keep = (p.only == nullptr || (idx < p.NB && p.only[idx] != 0)) &&
+                        (p.skip == nullptr || (idx < p.NB && p.skip[idx] == 0));
+      tiles[j] = (keep && n > (u64)SMALL_TILE) ? (n + p.rtile - 1) / p.rtile : 0;
+      smp[j] = n < (u64)p.s ? n : (u64)p.s;
+      small[j] = p.only == nullptr && n > 0 && n <= (u64)SMALL_TILE;
+      st += tiles[j];
+      sl += tiles[j] ? 1 : 0;
+      ss += smp[j];
+      sm += small[j] ? 1 : 0;
     }
-    // with a filter, only the listed large blocks are planned (small blocks
-    // and sample offsets are unaffected by it)
-    const bool keep = (p.only == nullptr || (idx < p.NB && p.only[idx] != 0)) &&
-                      (p.skip == nullptr || (idx < p.NB && p.skip[idx] == 0));
-    const u64 tiles = (keep && n > (u64)SMALL_TILE) ? (n + p.rtile - 1) / p.rtile : 0;
-    const u64 smp = n < (u64)p.s ? n : (u64)p.s;
-    const u64 small = (p.only == nullptr && n > 0 && n <= (u64)SMALL_TILE) ? 1 : 0;
-    u64 tot;
-    u64 ex = block_exclusive_scan<1024>(tiles, s_w, tot);
-    if (idx < p.NB) p.tstart[idx] = (u32)(carry_t + ex);
-    carry_t += tot;
-    ex = block_exclusive_scan<1024>(tiles ? 1 : 0, s_w, tot);
-    if (tiles) p.large_list[carry_l + ex] = idx;
-    carry_l += tot;
-    ex = block_exclusive_scan<1024>(smp, s_w, tot);
-    if (idx < p.NB) p.samp_start[idx] = carry_s + ex;
-    carry_s += tot;
-    ex = block_exclusive_scan<1024>(small, s_w, tot);
-    if (small) p.small_list[carry_m + ex] = idx;
-    carry_m += tot;
+    u64 tot_t, tot_l, tot_s, tot_m;
+    u64 et = carry_t + block_exclusive_scan<1024>(st, s_w, tot_t);
+    u64 el = carry_l + block_exclusive_scan<1024>(sl, s_w, tot_l);
+    u64 es = carry_s + block_exclusive_scan<1024>(ss, s_w, tot_s);
+    u64 em = carry_m + block_exclusive_scan<1024>(sm, s_w, tot_m);
+#pragma unroll
+    for (u32 j = 0; j < BPT; ++j) {
+      const u32 idx = i0 + j;
+      if (idx < p.NB) {
+        p.tstart[idx] = (u32)et;
+        p.samp_start[idx] = es;
+      }
+      if (tiles[j]) p.large_list[el++] = idx;
+      if (small[j]) p.small_list[em++] = idx;
+      et += tiles[j];
+      es += smp[j];
+    }
+    carry_t += tot_t;
+    carry_l += tot_l;
+    carry_s += tot_s;
+    carry_m += tot_m;
   }
   if (tid == 0) p.tstart[p.NB] = (u32)carry_t;
   __syncthreads();
@@ -125,17 +146,28 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
     __syncthreads();
     const u32 rmin = nbx ? s_rmin : 0;
     u64 carry_r = 0, carry_q = 0;
-    for (u32 base = 0; base < nbx; base += 1024) {
-      const u32 jx = base + tid;
-      u64 tiles = 0;
-      if (jx < nbx) {
-        const u32 blk = p.large_list[x + nq * jx];
-        tiles = p.tstart[blk + 1] - p.tstart[blk];
+    for (u32 base = 0; base < nbx; base += 1024 * BPT) {
+      const u32 j0 = base + tid * BPT;
+      u32 tl[BPT];
+      u64 sr = 0, sq = 0;
+#pragma unroll
+      for (u32 j = 0; j < BPT; ++j) {
+        tl[j] = 0;
+        if (j0 + j < nbx) {
+          const u32 blk = p.large_list[x + nq * (j0 + j)];
+          tl[j] = p.tstart[blk + 1] - p.tstart[blk];
+        }
+        sr += tl[j] ? tl[j] - rmin : 0;
+        sq += tl[j];
       }
       u64 tot, totq;
-      const u64 ex = block_exclusive_scan<1024>(tiles ? tiles - rmin : 0, s_w, tot);
-      block_exclusive_scan<1024>(tiles, s_w, totq);
-      if (jx < nbx) p.rem_prefix[x + nq * jx] = (u32)(carry_r + ex);
+      u64 er = carry_r + block_exclusive_scan<1024>(sr, s_w, tot);
+      block_exclusive_scan<1024>(sq, s_w, totq);
+#pragma unroll
+      for (u32 j = 0; j < BPT; ++j) {
+        if (j0 + j < nbx) p.rem_prefix[x + nq * (j0 + j)] = (u32)er;
+        er += tl[j] ? tl[j] - rmin : 0;
+      }
       carry_r += tot;
       carry_q += totq;
     }
@@ -342,57 +374,82 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
 }
 
 // Presorted large blocks (step 1 needs no radix pass for them; TimSort's runs
-// are the same idea): one workgroup per radix tile of the full plan writes the
-// tile's keys (mapped to the unsigned order) and values to the local sort's
-// output.  A non-decreasing block is copied; a non-increasing one is reversed
+// are the same idea): a workgroup takes PRESORTED_TPW consecutive radix tiles
+// of the full plan and writes their keys (mapped to the unsigned order) and
+// values to the local sort's output.  A non-decreasing block is copied; a non-increasing one is reversed
 // run by run: the key at block position x whose run of equal keys is [a, b)
 // goes to n - b + (x - a), which keeps equal keys in input order (stable).
 // Runs are found from the neighbours in the common case of distinct keys, by
 // binary search in the block otherwise.  Tiles of other blocks leave at once.
+constexpr u32 PRESORTED_TPW = 1;  // radix tiles per workgroup of k_presorted
+
 template <typename K, bool HASV>
 __global__ __launch_bounds__(256) void k_presorted(Plan p, const K* __restrict__ src, const u32* __restrict__ srcv,
                                                    K* __restrict__ dst, u32* __restrict__ dstv) {
-  const u32 t = blockIdx.x, tid = threadIdx.x;
-  if (t >= p.tstart[p.NB]) return;
-  const u32 blk = find_seg(p.tstart, p.NB, t);
-  const u32 f = p.presorted[blk];
-  if (f == 0) return;
-  const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
-  const u64 tbase = bs + (u64)(t - p.tstart[blk]) * p.rtile;
-  const u32 tile_n = be - tbase < (u64)p.rtile ? (u32)(be - tbase) : p.rtile;
-  const u64 vgen = bs - p.seg[blk / p.P];  // generated values: input position inside the instance
-  const u64 n = be - bs;
-  for (u32 i = tid; i < tile_n; i += 256) {
-    const u64 x = tbase + i;
-    const K k = key_in<K>(src[x], p.kx_top, p.kx_fm);
-    u32 v = 0;
-    if (HASV) v = srcv != nullptr ? srcv[x] : (u32)(vgen + (x - bs));
-    u64 o = x;
-    if ((f & 1u) == 0) {
-      // non-increasing: the run of k is [a, b) (block-relative)
-      const u64 xr = x - bs;
-      const bool eq_prev = xr > 0 && key_in<K>(src[x - 1], p.kx_top, p.kx_fm) == k;
-      const bool eq_next = xr + 1 < n && key_in<K>(src[x + 1], p.kx_top, p.kx_fm) == k;
-      u64 a = xr, b = xr + 1;
-      if (eq_prev || eq_next) {
-        // keys above k come first, then the run of k, then keys below it
-        u64 lo = 0, hi = n;
-        while (lo < hi) {
-          const u64 mid = lo + ((hi - lo) >> 1);
-          if (key_in<K>(src[bs + mid], p.kx_top, p.kx_fm) > k) lo = mid + 1; else hi = mid;
-        }
-        a = lo;
-        hi = n;
-        while (lo < hi) {
-          const u64 mid = lo + ((hi - lo) >> 1);
-          if (key_in<K>(src[bs + mid], p.kx_top, p.kx_fm) >= k) lo = mid + 1; else hi = mid;
-        }
-        b = lo;
+  constexpr int U = 8;  // elements per thread per round, their loads issued together
+  __shared__ u32 s_blk;
+  const u32 tid = threadIdx.x;
+  const u32 ntiles = p.tstart[p.NB];
+  const u32 t0 = blockIdx.x * PRESORTED_TPW;
+  if (t0 >= ntiles) return;
+  if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t0);
+  __syncthreads();
+  u32 blk = s_blk;
+  const u32 t1 = t0 + PRESORTED_TPW < ntiles ? t0 + PRESORTED_TPW : ntiles;
+  for (u32 t = t0; t < t1; ++t) {
+    while (t >= p.tstart[blk + 1]) ++blk;  // consecutive tiles: the same block or a later one
+    const u32 f = p.presorted[blk];
+    if (f == 0) continue;
+    const u64 bs = p.blk_start[blk], be = p.blk_start[blk + 1];
+    const u64 tbase = bs + (u64)(t - p.tstart[blk]) * p.rtile;
+    const u32 tile_n = be - tbase < (u64)p.rtile ? (u32)(be - tbase) : p.rtile;
+    const u64 vgen = bs - p.seg[blk / p.P];  // generated values: input position inside the instance
+    const u64 n = be - bs;
+    for (u32 i0 = 0; i0 < tile_n; i0 += 256 * U) {
+      K kk[U];
+      u32 vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const u32 i = i0 + (u32)u * 256 + tid;
+        const u64 x = tbase + i;
+        kk[u] = i < tile_n ? src[x] : (K)0;
+        vv[u] = 0;
+        if (HASV && i < tile_n) vv[u] = srcv != nullptr ? srcv[x] : (u32)(vgen + (x - bs));
       }
-      o = bs + (n - b) + (xr - a);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const u32 i = i0 + (u32)u * 256 + tid;
+        if (i >= tile_n) continue;
+        const u64 x = tbase + i;
+        const K k = key_in<K>(kk[u], p.kx_top, p.kx_fm);
+        u64 o = x;
+        if ((f & 1u) == 0) {
+          // non-increasing: the run of k is [a, b) (block-relative)
+          const u64 xr = x - bs;
+          const bool eq_prev = xr > 0 && key_in<K>(src[x - 1], p.kx_top, p.kx_fm) == k;
+          const bool eq_next = xr + 1 < n && key_in<K>(src[x + 1], p.kx_top, p.kx_fm) == k;
+          u64 a = xr, b = xr + 1;
+          if (eq_prev || eq_next) {
+            // keys above k come first, then the run of k, then keys below it
+            u64 lo = 0, hi = n;
+            while (lo < hi) {
+              const u64 mid = lo + ((hi - lo) >> 1);
+              if (key_in<K>(src[bs + mid], p.kx_top, p.kx_fm) > k) lo = mid + 1; else hi = mid;
+            }
+            a = lo;
+            hi = n;
+            while (lo < hi) {
+              const u64 mid = lo + ((hi - lo) >> 1);
+              if (key_in<K>(src[bs + mid], p.kx_top, p.kx_fm) >= k) lo = mid + 1; else hi = mid;
+            }
+            b = lo;
+          }
+          o = bs + (n - b) + (xr - a);
+        }
+        dst[o] = k;
+        if (HASV) dstv[o] = vv[u];
+      }
     }
-    dst[o] = k;
-    if (HASV) dstv[o] = v;
   }
 }
 
@@ -1475,7 +1532,8 @@ template <typename K, bool HASV>
 void launch_presorted(const Plan& p, const K* src, const u32* srcv, K* dst, u32* dstv, hipStream_t s) {
   if (p.max_tiles == 0) return;
   const int pe_ = prof_begin(s);
-  hipLaunchKernelGGL((k_presorted<K, HASV>), dim3(p.max_tiles), dim3(256), 0, s, p, src, srcv, dst, dstv);
+  hipLaunchKernelGGL((k_presorted<K, HASV>), dim3((p.max_tiles + PRESORTED_TPW - 1) / PRESORTED_TPW), dim3(256), 0, s, p,
+                     src, srcv, dst, dstv);
   prof_end(pe_, "presorted", s);
 }
 

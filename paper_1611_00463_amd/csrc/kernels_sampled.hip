@@ -99,18 +99,13 @@ __global__ __launch_bounds__(256) void k_samp_meta(Plan p, SampPlan sp) {
 template <typename K>
 __global__ __launch_bounds__(256) void k_samp_gather(Plan p, SampPlan sp, const K* __restrict__ sorted,
                                                      K* __restrict__ skeys, u32* __restrict__ svals) {
-  const u64 u = (u64)blockIdx.x * 256 + threadIdx.x;
+  __shared__ u32 s_rng[2];
+  const u64 u0 = (u64)blockIdx.x * 256, u = u0 + threadIdx.x;
   const u32 P = p.P, NB = p.B * P;
-  if (u >= sp.sseg[p.B]) return;
-  u32 bi = 0;
-  {
-    u32 lo = 0, hi = NB;
-    while (hi - lo > 1) {
-      const u32 mid = (lo + hi) >> 1;
-      if (sp.sbs[mid] <= u) lo = mid; else hi = mid;
-    }
-    bi = lo;
-  }
+  const u64 total = sp.sseg[p.B];
+  if (u0 >= total) return;  // the whole workgroup
+  const u32 bi = wg_find_seg(sp.sbs, NB, u, u0, min(u0 + 255, total - 1), s_rng);
+  if (u >= total) return;
   const u64 off = u - sp.sbs[bi];
   const u64* sc = sp.scuts + (u64)bi * (P + 1);
   if (u < sp.sbs[bi] || off >= sc[P]) return;  // a gap between instances

@@ -13,9 +13,12 @@ namespace lbs {
 // starts floor(j n_i / s_i) (the regular sampling of PSRS).
 template <typename K>
 __global__ __launch_bounds__(256) void k_samples(Plan p, const K* __restrict__ sorted, u64 max_samples) {
-  const u64 x = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= max_samples || x >= p.samp_start[p.NB]) return;
-  const u32 blk = find_seg(p.samp_start, p.NB, x);
+  __shared__ u32 s_rng[2];
+  const u64 x0 = (u64)blockIdx.x * 256, x = x0 + threadIdx.x;
+  const u64 total = min(max_samples, (u64)p.samp_start[p.NB]);
+  if (x0 >= total) return;  // the whole workgroup
+  const u32 blk = wg_find_seg(p.samp_start, p.NB, x, x0, min(x0 + 255, total - 1), s_rng);
+  if (x >= total) return;
   const u64 j = x - p.samp_start[blk];
   const u64 si = p.samp_start[blk + 1] - p.samp_start[blk];
   const u64 bs = p.blk_start[blk];

@@ -227,6 +227,24 @@ __device__ inline u32 find_seg(const T* prefix, u32 n, u64 t) {
   return lo;
 }
 
+// find_seg for every thread of a workgroup whose thread i asks for x0 + i
+// (x <= xlast for the threads that ask at all): two threads search for x0 and
+// xlast over all n segments, every thread then only between those two (a few
+// steps in place of log2 n dependent loads per thread).  s_rng: two words of
+// LDS.  Called by every thread of the workgroup (it has a barrier).
+template <typename T>
+__device__ inline u32 wg_find_seg(const T* prefix, u32 n, u64 x, u64 x0, u64 xlast, u32* s_rng) {
+  if (threadIdx.x == 0) s_rng[0] = find_seg(prefix, n, x0);
+  if (threadIdx.x == 1) s_rng[1] = find_seg(prefix, n, xlast);
+  __syncthreads();
+  u32 lo = s_rng[0], hi = s_rng[1] + 1;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if ((u64)prefix[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Number of elements of sorted a[0, n) that are < x (lower) or <= x (upper).
 template <typename K, bool UPPER>
 __device__ inline u64 bsearch_count(const K* a, u64 lo, u64 hi, K x) {
