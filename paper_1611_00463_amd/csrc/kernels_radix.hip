@@ -320,11 +320,14 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
           done = done || key == hot;
         }
       }
-      for (int r = 0; r < 3; ++r) {
+      // leader rounds on the first key of each load batch only: they find
+      // the hot key of duplicate-heavy data, and on spread keys they cost
+      // more than the collisions they would save
+      for (int r = 0; r < (u == 0 ? 3 : 0); ++r) {
         const u64 act = __ballot(!done);
         if (act == 0) break;
         const int leader = __ffsll((unsigned long long)act) - 1;
-        const K lk = __shfl(key, leader);
+        const K lk = lane_value(key, leader);
         const bool same = !done && key == lk;
         const u64 sm = __ballot(same);
         if (__popcll(sm) < 2) break;  // no duplicate of the leader: leave all to the bulk path
@@ -355,7 +358,7 @@ __global__ __launch_bounds__(SORT_NT) void k_hist(Plan p, const K* __restrict__ 
 #pragma unroll
         for (int q = DLO; q < D; ++q) {
           const u32 d = (u32)((key >> (q * RADIX_BITS)) & (RADIX - 1));
-          const u32 d0 = (u32)__shfl((int)d, first);
+          const u32 d0 = lane_value(d, first);
           if (__ballot(!done && d != d0) == 0) {
             if (lane == (u32)first) atomicAdd(&h[q * RADIX + d0], (u32)__popcll(rest));
           } else if (!done) {

@@ -227,6 +227,12 @@ __device__ inline u32 find_seg(const T* prefix, u32 n, u64 t) {
   return lo;
 }
 
+// x of lane `l` (the same l in every lane), read without LDS.
+__device__ inline u32 lane_value(u32 x, int l) { return (u32)__builtin_amdgcn_readlane((int)x, l); }
+__device__ inline u64 lane_value(u64 x, int l) {
+  return ((u64)lane_value((u32)(x >> 32), l) << 32) | lane_value((u32)x, l);
+}
+
 // find_seg for every thread of a workgroup whose thread i asks for x0 + i
 // (x <= xlast for the threads that ask at all): two threads search for x0 and
 // xlast over all n segments, every thread then only between those two (a few
