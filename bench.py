@@ -289,7 +289,8 @@ def run_batch(args, steps, warmup, tune=True, check=True):
     keys, vals, seg, sizes = datagen.batch_u32_torch(B, 4, device="cuda")
     total = int(sizes.sum())
     tuned = None
-    force = dict(fanin=args.fanin, merge_tile=args.merge_tile, radix_tile=args.radix_tile, handler=args.handler)
+    force = dict(fanin=args.fanin, merge_tile=args.merge_tile, radix_tile=args.radix_tile, handler=args.handler,
+                 presorted=args.presorted)
     if tune and not any(force.values()):
         print("[bench] autotuning the batch", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
@@ -650,7 +651,7 @@ def measure_sort(w, args, steps, warmup, profile=True, tune=False):
     ws = L.Workspace(dev)
     vt = (L.VAL_U32 if vals is not None else L.VAL_INDEX) if has_v else L.NOVAL
     tuned = None
-    if tune and not (args.fanin or args.merge_tile or args.radix_tile or args.handler):
+    if tune and not (args.fanin or args.merge_tile or args.radix_tile or args.handler or args.presorted):
         print(f"[bench] autotuning {w['tag']}", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         tuned = L.autotune(L.key_code(keys.dtype), vt, w["P"], keys=keys, vals=vals)
@@ -659,10 +660,11 @@ def measure_sort(w, args, steps, warmup, profile=True, tune=False):
     def step():
         if not has_v:
             return L.sort_keys(keys, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
-                               keys_out=kout, workspace=ws, radix_tile=args.radix_tile, handler=args.handler)
+                               keys_out=kout, workspace=ws, radix_tile=args.radix_tile, handler=args.handler,
+                               presorted=args.presorted)
         return L.sort_pairs(keys, vals, w["P"], s=w["s"], fanin=args.fanin, merge_tile=args.merge_tile,
                             keys_out=kout, vals_out=vout, workspace=ws, radix_tile=args.radix_tile,
-                            handler=args.handler)
+                            handler=args.handler, presorted=args.presorted)
 
     for _ in range(warmup):
         r = step()
@@ -695,7 +697,8 @@ def measure_sort(w, args, steps, warmup, profile=True, tune=False):
     imb = {"max_over_mean": round(float(counts.max() / counts.mean()), 6), "min": int(counts.min()),
            "max": int(counts.max()), "P": w["P"]}
     used = L.resolve_params(L.key_code(keys.dtype), vt, w["P"], w["n"], s=w["s"], fanin=args.fanin,
-                            merge_tile=args.merge_tile, radix_tile=args.radix_tile, handler=args.handler)
+                            merge_tile=args.merge_tile, radix_tile=args.radix_tile, handler=args.handler,
+                            presorted=args.presorted)
     out = dict(ms=ms, value=w["n"] / (ms / 1e3) / 1e9, prof=prof, ms_prof=ms_prof, imbalance=imb, settings=used,
                autotuned=tuned, kb=keys.element_size(), vb=4 if has_v else 0, dtype=KEY_NAMES[str(keys.dtype)])
     del keys, vals, kout, vout, ws, r
@@ -746,6 +749,8 @@ def main():
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--radix-tile", type=int, default=0)
     ap.add_argument("--handler", type=int, default=0, help="1: F-way passes, 2: one pass (0: tuned)")
+    ap.add_argument("--presorted", type=int, default=0,
+                    help="1: detect presorted blocks, 2: ignore them (0: tuned)")
     ap.add_argument("--no-loop", action="store_true", help="batch: leave out the per-instance loop (profiling)")
     ap.add_argument("--batch", type=int, default=4096, help="instances for --workload batch")
     ap.add_argument("--serve-requests", type=int, default=10000, help="requests for --workload serve")

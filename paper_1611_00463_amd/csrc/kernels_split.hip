@@ -23,7 +23,8 @@ __global__ __launch_bounds__(256) void k_samples(Plan p, const K* __restrict__ s
   const u64 si = p.samp_start[blk + 1] - p.samp_start[blk];
   const u64 bs = p.blk_start[blk];
   const u64 n = p.blk_start[blk + 1] - bs;
-  const u64 pos = (u64)(((unsigned __int128)j * n) / si);
+  // j < si <= n < 2^32 (the plan bounds block sizes), so j n fits 64 bits
+  const u64 pos = j * n / si;
   ((K*)p.samples)[x] = sorted[bs + pos];
 }
 
@@ -136,8 +137,9 @@ __global__ __launch_bounds__(256) void k_search(Plan p, const K* __restrict__ so
   u64 wlo = 0, whi = n;
   if (si > 0) {
     const u64 j = upper ? bsearch_count<K, true>(smp, sa, sa + si, v) - sa : bsearch_count<K, false>(smp, sa, sa + si, v) - sa;
-    if (j > 0) wlo = (u64)(((unsigned __int128)(j - 1) * n) / si) + 1;
-    if (j < si) whi = (u64)(((unsigned __int128)j * n) / si);
+    // j <= si <= n < 2^32: the products fit 64 bits
+    if (j > 0) wlo = (j - 1) * n / si + 1;
+    if (j < si) whi = j * n / si;
   }
   const u64 r = upper ? bsearch_count<K, true>(sorted + bs, wlo, whi, v) : bsearch_count<K, false>(sorted + bs, wlo, whi, v);
   (upper ? p.hi : p.lo)[(u64)blk * per + k] = r;

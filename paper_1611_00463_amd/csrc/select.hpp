@@ -55,7 +55,9 @@ __device__ inline u64 wave_select(const K* __restrict__ src, u64 roff, u64 lo, u
       pvalid[m] = W > 0;
       u64 at = lo_o + (W * (qi + 1)) / (QPR + 1);
       if (round == 0 && wsum > 0) {
-        const u64 guess = lo_o + (u64)(((unsigned __int128)(a - lsum) * W) / wsum);
+        // only a starting point (any position in the window is correct), so
+        // floating point is enough: 0 <= a - sum lo <= sum W keeps it in range
+        const u64 guess = lo_o + (u64)((double)(a - lsum) * (double)W / (double)wsum);
         const u64 d = W / 64 > 1 ? W / 64 : 1;
         const int k = (int)qi - QPR / 2;  // -QPR/2 .. QPR/2-1
         const u64 mag = d << (2 * (k < 0 ? -k - 1 : k));
