@@ -54,12 +54,10 @@ __device__ inline u64 block_exclusive_scan(u64 v, u64* s_w, u64& total) {
 __global__ __launch_bounds__(1024) void k_plan(Plan p) {
   __shared__ u64 s_w[16];
   __shared__ u32 s_bad;
-  __shared__ u32 s_rmin;
+  __shared__ u32 s_qmin[NQ];
+  __shared__ u64 s_qb1[NQ], s_qb2[NQ];
   const u32 tid = threadIdx.x;
-  if (tid == 0) {
-    s_bad = (p.seg[0] != 0 || p.seg[p.B] != p.total_n) ? 1u : 0u;
-    s_rmin = 0xFFFFFFFFu;
-  }
+  if (tid == 0) s_bad = (p.seg[0] != 0 || p.seg[p.B] != p.total_n) ? 1u : 0u;
   __syncthreads();
   for (u32 b = tid; b < p.B; b += 1024) {
     if (p.seg[b + 1] < p.seg[b]) s_bad = 1u;
@@ -131,54 +129,77 @@ __global__ __launch_bounds__(1024) void k_plan(Plan p) {
   __syncthreads();
   // Tile queues: large block j goes to queue j % nq.  Per queue: block count,
   // fewest tiles (rmin), prefix of the tiles beyond the interleaved head, and
-  // the queue's first slot in the look-back status array.
+  // the queue's first slot in the look-back status array.  All queues in one
+  // scan: the large blocks in queue-major order (queue x's blocks jx = 0, 1,
+  // ... at k = qoff(x) + jx), each queue's prefix being the scan minus its
+  // value at the queue's first block.
   const u32 nl = (u32)carry_l;
   const u32 nq = p.nq;
-  u64 qbase = 0;
-  for (u32 x = 0; x < nq; ++x) {
-    const u32 nbx = nl > x ? (nl - x + nq - 1) / nq : 0;
-    if (tid == 0) s_rmin = 0xFFFFFFFFu;
-    __syncthreads();
-    for (u32 jx = tid; jx < nbx; jx += 1024) {
-      const u32 blk = p.large_list[x + nq * jx];
-      atomicMin(&s_rmin, p.tstart[blk + 1] - p.tstart[blk]);
-    }
-    __syncthreads();
-    const u32 rmin = nbx ? s_rmin : 0;
-    u64 carry_r = 0, carry_q = 0;
-    for (u32 base = 0; base < nbx; base += 1024 * BPT) {
-      const u32 j0 = base + tid * BPT;
-      u32 tl[BPT];
-      u64 sr = 0, sq = 0;
+  const u32 qa = nl / nq, qr = nl % nq;  // queue x holds qa + (x < qr) blocks
+  auto qoff = [&](u32 x) { return x * qa + (x < qr ? x : qr); };
+  if (tid < NQ) {
+    s_qmin[tid] = 0xFFFFFFFFu;
+    s_qb1[tid] = s_qb2[tid] = 0;
+  }
+  __syncthreads();
+  for (u32 j = tid; j < nl; j += 1024) {
+    const u32 blk = p.large_list[j];
+    atomicMin(&s_qmin[j % nq], p.tstart[blk + 1] - p.tstart[blk]);
+  }
+  __syncthreads();
+  u64 carry_r = 0, carry_q = 0;
+  for (u32 base = 0; base < nl; base += 1024 * BPT) {
+    const u32 k0 = base + tid * BPT;
+    u32 tl[BPT], jj[BPT], xx[BPT];
+    u64 sr = 0, sq = 0;
 #pragma unroll
-      for (u32 j = 0; j < BPT; ++j) {
-        tl[j] = 0;
-        if (j0 + j < nbx) {
-          const u32 blk = p.large_list[x + nq * (j0 + j)];
-          tl[j] = p.tstart[blk + 1] - p.tstart[blk];
+    for (u32 i = 0; i < BPT; ++i) {
+      const u32 k = k0 + i;
+      tl[i] = 0;
+      xx[i] = 0;
+      jj[i] = 0;
+      if (k < nl) {
+        // queue and index of the k-th block in queue-major order
+        const u32 head = qr * (qa + 1);
+        const u32 x = k < head ? k / (qa + 1) : qr + (k - head) / qa;
+        const u32 jx = k - qoff(x);
+        xx[i] = x;
+        jj[i] = x + nq * jx;
+        const u32 blk = p.large_list[jj[i]];
+        tl[i] = p.tstart[blk + 1] - p.tstart[blk];
+      }
+      sr += tl[i] ? tl[i] - s_qmin[xx[i]] : 0;
+      sq += tl[i];
+    }
+    u64 tot, totq;
+    u64 er = carry_r + block_exclusive_scan<1024>(sr, s_w, tot);
+    u64 eq = carry_q + block_exclusive_scan<1024>(sq, s_w, totq);
+#pragma unroll
+    for (u32 i = 0; i < BPT; ++i) {
+      const u32 k = k0 + i;
+      if (k < nl) {
+        if (k == qoff(xx[i])) {  // the queue's first block: its bases
+          s_qb1[xx[i]] = er;
+          s_qb2[xx[i]] = eq;
         }
-        sr += tl[j] ? tl[j] - rmin : 0;
-        sq += tl[j];
+        p.rem_prefix[jj[i]] = (u32)er;  // made queue-relative below
       }
-      u64 tot, totq;
-      u64 er = carry_r + block_exclusive_scan<1024>(sr, s_w, tot);
-      block_exclusive_scan<1024>(sq, s_w, totq);
-#pragma unroll
-      for (u32 j = 0; j < BPT; ++j) {
-        if (j0 + j < nbx) p.rem_prefix[x + nq * (j0 + j)] = (u32)er;
-        er += tl[j] ? tl[j] - rmin : 0;
-      }
-      carry_r += tot;
-      carry_q += totq;
+      er += tl[i] ? tl[i] - s_qmin[xx[i]] : 0;
+      eq += tl[i];
     }
-    if (tid == 0) {
-      p.counters[C_QPARAM + 4 * x + 0] = nbx;
-      p.counters[C_QPARAM + 4 * x + 1] = rmin;
-      p.counters[C_QPARAM + 4 * x + 2] = (u32)qbase;
-      p.counters[C_QPARAM + 4 * x + 3] = (u32)carry_q;
-    }
-    qbase += carry_q;
-    __syncthreads();
+    carry_r += tot;
+    carry_q += totq;
+  }
+  __syncthreads();
+  for (u32 j = tid; j < nl; j += 1024) p.rem_prefix[j] -= (u32)s_qb1[j % nq];
+  if (tid < nq) {
+    const u32 x = tid, nbx = qa + (x < qr ? 1u : 0u);
+    const u64 qbase = nbx ? s_qb2[x] : carry_q;
+    const u64 qend = x + 1 < nq && qa + (x + 1 < qr ? 1u : 0u) ? s_qb2[x + 1] : carry_q;
+    p.counters[C_QPARAM + 4 * x + 0] = nbx;
+    p.counters[C_QPARAM + 4 * x + 1] = nbx ? s_qmin[x] : 0;
+    p.counters[C_QPARAM + 4 * x + 2] = (u32)qbase;
+    p.counters[C_QPARAM + 4 * x + 3] = (u32)(nbx ? qend - qbase : 0);
   }
   if (tid == 0) {
     p.samp_start[p.NB] = carry_s;

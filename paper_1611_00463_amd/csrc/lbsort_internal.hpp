@@ -265,7 +265,10 @@ __device__ inline u64 bsearch_count(const K* a, u64 lo, u64 hi, K x) {
 
 // Block of instance b, processor i: start = seg[b] + floor(i * n_b / P).
 __device__ inline u64 block_begin(const u64* seg, u32 b, u32 i, u32 P) {
-  u64 a = seg[b], n = seg[b + 1] - seg[b];
+  const u64 a = seg[b], n = seg[b + 1] - seg[b];
+  // i <= P <= 1024: below 2^53 keys the product fits 64 bits (a 128-bit
+  // division is a long software loop)
+  if (n < (1ull << 53)) return a + (u64)i * n / P;
   return a + (u64)(((unsigned __int128)i * n) / P);
 }
 
