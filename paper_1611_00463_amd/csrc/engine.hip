@@ -17,6 +17,7 @@ namespace lbs {
 
 void launch_plan(const Plan& p, hipStream_t s);
 void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s);
+void launch_fill_set(const FillSet& f, hipStream_t s);
 template <typename K>
 void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo = 0);
 template <typename K, bool HASV>
@@ -431,15 +432,24 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   auto dk = [&](u32 j) -> K* { return ((S - 1 - j) % 2 == 0) ? kout : tk; };
   auto dv = [&](u32 j) -> u32* { return ((S - 1 - j) % 2 == 0) ? vout : tv; };
 
-  launch_fill32(p.counters, C_COUNT, 0, st);
-  if (sh.has_large) {
-    launch_fill32(p.hist, (u64)p.NB * sh.D * RADIX, 0, st);
-    launch_fill32((u32*)p.status, sh.max_tiles * RADIX * 2, 0, st);
-    if (sh.presort == LBSORT_PRESORTED_DETECT) launch_fill32(presorted, p.NB, 3u, st);
-  }
-  launch_plan(p, st);
   // the fix-up path of 64-bit keys needs the counts of the three top digits only
   const bool hybrid = sizeof(K) == 8 && hybrid_local_sort();
+  {
+    // every word that must start at a known value, in one launch
+    FillSet f;
+    f.add(p.counters, C_COUNT, 0);
+    if (sh.has_large) {
+      f.add(p.hist, (u64)p.NB * sh.D * RADIX, 0);
+      f.add((u32*)p.status, sh.max_tiles * RADIX * 2, 0);
+      if (sh.presort == LBSORT_PRESORTED_DETECT) f.add(presorted, p.NB, 3u);
+      if (sizeof(K) == 8 && hybrid) {
+        f.add(p.gflags, p.NB, 0);
+        f.add(p.gflags2, p.NB, 0);
+      }
+    }
+    launch_fill_set(f, st);
+  }
+  launch_plan(p, st);
   // the fix-up path's top-digit passes leave out a digit that no block needs
   Plan ph = px;
   if (hybrid) {
@@ -474,8 +484,6 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         u32* const FV = dv(sh.D - 1);
         K* const O = F == kout ? tk : kout;
         u32* const OV = HASV ? (FV == vout ? tv : vout) : nullptr;
-        launch_fill32(p.gflags, p.NB, 0, st);
-        launch_fill32(p.gflags2, p.NB, 0, st);
         // the passes that run read the input first and leave their result in O
         ph.pass_out = O;
         ph.pass_outv = OV;
@@ -488,7 +496,12 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         Plan q = p;
         q.only = p.gflags2;
         q.epoch_base = 8;  // the status words of the passes above stay valid for epochs 6..8
-        launch_fill32(p.counters + C_TICKET, NQ * sh.D, 0, st);
+        {
+          FillSet f;
+          f.add(p.counters + C_TICKET, NQ * sh.D, 0);
+          f.add(p.hist, (u64)p.NB * sh.D * RADIX, 0);
+          launch_fill_set(f, st);
+        }
         launch_plan(q, st);
         Plan qx = q;
         qx.kx_top = top;
@@ -502,7 +515,6 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         qx.pass_outv = FV;
         qx.pass_tmp = O;
         qx.pass_tmpv = OV;
-        launch_fill32(p.hist, (u64)p.NB * sh.D * RADIX, 0, st);
         launch_hist<K>(qx, kin, st);
         for (u32 j = 0; j < sh.D; ++j) launch_onesweep<K, HASV>(qx, kin, vin, F, FV, j, st);
       } else {

@@ -235,6 +235,13 @@ __global__ __launch_bounds__(256) void k_tile_desc(Plan p) {
   }
 }
 
+// Several fills in one launch (FillSet: up to FILL_MAX ranges).
+__global__ void k_fill_set(FillSet f) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (int r = 0; r < f.count; ++r)
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < f.n[r]; i += stride) f.a[r][i] = f.v[r];
+}
+
 __global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) a[i] = v;
 }
@@ -1529,6 +1536,15 @@ void launch_plan(const Plan& p, hipStream_t s) {
     hipLaunchKernelGGL(k_tile_desc, dim3((p.max_tiles + 255) / 256), dim3(256), 0, s, p);
     prof_end(pe_, p.only ? "tile_desc_fallback" : "tile_desc", s);
   }
+}
+
+void launch_fill_set(const FillSet& f, hipStream_t s) {
+  u64 most = 0;
+  for (int r = 0; r < f.count; ++r) most = f.n[r] > most ? f.n[r] : most;
+  if (most == 0) return;
+  u64 blocks = (most + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_fill_set, dim3((u32)blocks), dim3(256), 0, s, f); prof_end(pe_, "fill", s); }
 }
 
 void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s) {

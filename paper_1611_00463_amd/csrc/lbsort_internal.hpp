@@ -305,6 +305,22 @@ struct TileQueue {
   }
 };
 
+// Ranges of 32-bit words to set in one launch.
+constexpr int FILL_MAX = 6;
+struct FillSet {
+  u32* a[FILL_MAX];
+  u64 n[FILL_MAX];
+  u32 v[FILL_MAX];
+  int count = 0;
+  void add(u32* p, u64 words, u32 value) {
+    if (words == 0) return;
+    a[count] = p;
+    n[count] = words;
+    v[count] = value;
+    ++count;
+  }
+};
+
 // Optional per-launch event timing (lbsort_profile_enable).
 int prof_begin(hipStream_t s);
 void prof_end(int id, const char* name, hipStream_t s);
