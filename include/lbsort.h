@@ -232,6 +232,33 @@ int lbsort_search(int key_type, const void *sorted_keys, uint64_t n, const void 
                   uint32_t *part_out, void *stream);
 
 /*
+ * Search index over sorted data (Section III, Section IV.C: the sorted result
+ * can be searched; the same queries as lbsort_search, with
+ * fewer memory lines per query).  Level l >= 1 of the index holds the keys
+ * at positions i * 16^l of sorted_keys, n_l = ceil(n_{l-1} / 16) keys, up to
+ * the first level of at most 16 keys; each level starts on a 128-byte
+ * boundary.  A query reads one group of 16 keys per level (about
+ * log16(n) + 1 cache lines) instead of one line per halving of the range.
+ *
+ * lbsort_search_index_bytes: bytes of the index of n keys of key_type (0 when
+ * n <= 16, where no index is needed; 0 for an invalid key_type).
+ *
+ * lbsort_search_build_index: writes the index of sorted_keys (n keys, device)
+ * into index (device, caller-owned, lbsort_search_index_bytes(key_type, n)
+ * bytes, 128-byte aligned), asynchronously on `stream`.  The index stays valid
+ * while sorted_keys is unchanged.  Nothing is allocated.
+ *
+ * lbsort_search_indexed: lbsort_search with the index built for the same
+ * sorted_keys and n (index may be NULL when n <= 16); same arguments
+ * otherwise, bit-identical outputs.
+ */
+uint64_t lbsort_search_index_bytes(int key_type, uint64_t n);
+int lbsort_search_build_index(int key_type, const void *sorted_keys, uint64_t n, void *index, void *stream);
+int lbsort_search_indexed(int key_type, const void *sorted_keys, uint64_t n, const void *index,
+                          const void *queries, uint64_t nq, int upper, const uint64_t *part_offsets,
+                          uint32_t P, uint64_t *pos_out, uint32_t *part_out, void *stream);
+
+/*
  * Provenance of sorted entries (step 6 of Section IV keeps, for every entry,
  * the processor and the index it came from; Section IV.C exposes them).
  * src_index: count input positions (the vals_out of an LBSORT_VAL_INDEX sort

@@ -46,6 +46,11 @@ template <typename K>
 void launch_search(const K* a, u64 n, const K* q, u64 nq, bool upper, u64 top, u64 fm, const u64* G, u32 P,
                    u64* pos, u32* part, hipStream_t s);
 void launch_provenance(const u32* idx, u64 count, u64 n, u32 P, u32* blk, u32* off, hipStream_t s);
+template <typename K>
+void launch_search_index_build(const K* a, u64 n, void* index, hipStream_t s);
+template <typename K>
+void launch_search_indexed(const K* a, u64 n, const void* index, const K* q, u64 nq, bool upper, u64 top, u64 fm,
+                           const u64* G, u32 P, u64* pos, u32* part, hipStream_t s);
 
 static thread_local std::string g_last_error;
 
@@ -749,6 +754,57 @@ int lbsort_search(int key_type, const void* sorted_keys, uint64_t n, const void*
   else
     launch_search<u32>((const u32*)sorted_keys, n, (const u32*)queries, nq, upper != 0, top, fm, part_offsets, P,
                        pos_out, part_out, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return LBSORT_OK;
+}
+
+uint64_t lbsort_search_index_bytes(int key_type, uint64_t n) {
+  const u32 w = key_width(key_type);
+  if (!w) return 0;
+  return SearchIndexLayout(n, w).bytes;
+}
+
+int lbsort_search_build_index(int key_type, const void* sorted_keys, uint64_t n, void* index, void* stream) {
+  const u32 w = key_width(key_type);
+  if (!w) return fail(LBSORT_ERR_INVALID_ARG, "key_type must be one of LBSORT_U32..LBSORT_F64 (got %d)", key_type);
+  const SearchIndexLayout lay(n, w);
+  if (lay.bytes == 0) return LBSORT_OK;
+  if (!sorted_keys || !index) return fail(LBSORT_ERR_INVALID_ARG, "sorted_keys/index must not be NULL");
+  if ((uintptr_t)index % 128 != 0) return fail(LBSORT_ERR_INVALID_ARG, "index must be 128-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  if (w == 8)
+    launch_search_index_build<u64>((const u64*)sorted_keys, n, index, st);
+  else
+    launch_search_index_build<u32>((const u32*)sorted_keys, n, index, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return LBSORT_OK;
+}
+
+int lbsort_search_indexed(int key_type, const void* sorted_keys, uint64_t n, const void* index, const void* queries,
+                          uint64_t nq, int upper, const uint64_t* part_offsets, uint32_t P, uint64_t* pos_out,
+                          uint32_t* part_out, void* stream) {
+  const u32 w = key_width(key_type);
+  if (!w) return fail(LBSORT_ERR_INVALID_ARG, "key_type must be one of LBSORT_U32..LBSORT_F64 (got %d)", key_type);
+  if (upper != 0 && upper != 1) return fail(LBSORT_ERR_INVALID_ARG, "upper must be 0 or 1 (got %d)", upper);
+  if (nq == 0) return LBSORT_OK;
+  if (!queries || !pos_out) return fail(LBSORT_ERR_INVALID_ARG, "queries/pos_out must not be NULL");
+  if (n > 0 && !sorted_keys) return fail(LBSORT_ERR_INVALID_ARG, "sorted_keys must not be NULL");
+  if (SearchIndexLayout(n, w).bytes > 0 && !index)
+    return fail(LBSORT_ERR_INVALID_ARG, "index must not be NULL for n > 16 (lbsort_search_build_index)");
+  if (part_out && (!part_offsets || P < 1 || P > LBSORT_MAX_P))
+    return fail(LBSORT_ERR_INVALID_ARG, "part_out needs part_offsets and P in [1, %d]", LBSORT_MAX_P);
+  if (nq / 256 >= (1ull << 31)) return fail(LBSORT_ERR_UNSUPPORTED, "too many queries in one call");
+  u64 top, fm;
+  key_masks(key_type, top, fm);
+  hipStream_t st = (hipStream_t)stream;
+  if (w == 8)
+    launch_search_indexed<u64>((const u64*)sorted_keys, n, index, (const u64*)queries, nq, upper != 0, top, fm,
+                               part_offsets, P, pos_out, part_out, st);
+  else
+    launch_search_indexed<u32>((const u32*)sorted_keys, n, index, (const u32*)queries, nq, upper != 0, top, fm,
+                               part_offsets, P, pos_out, part_out, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(LBSORT_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
   return LBSORT_OK;

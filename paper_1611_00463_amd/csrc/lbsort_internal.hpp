@@ -321,6 +321,34 @@ struct FillSet {
   }
 };
 
+// Search index over n sorted keys: level l >= 1 holds the keys at positions
+// i * 16^l (the first key of every group of 16^l), n_l = ceil(n_{l-1} / 16)
+// of them, up to the first level of at most 16 keys; level 0 is the sorted
+// array itself.  Levels 1.. are stored one after another, each starting on a
+// 128-byte boundary.  Laid out on the host and passed to the kernels by
+// value (a level number is the same in every lane, so its fields are read
+// with scalar loads).
+constexpr u32 SI_FAN = 16;
+constexpr int SI_MAX_LEVELS = 16;  // 16^16 = 2^64
+struct SearchIndexLayout {
+  int top = 0;                   // the top level (0 when n <= 16: no index)
+  u64 n[SI_MAX_LEVELS + 1];      // keys per level (n[0] = n)
+  u64 off[SI_MAX_LEVELS + 1];    // byte offset of level l >= 1 in the index
+  u64 bytes = 0;
+  SearchIndexLayout(u64 keys, u32 key_bytes) {
+    n[0] = keys;
+    off[0] = 0;
+    u64 at = 0;
+    while (n[top] > SI_FAN) {
+      ++top;
+      n[top] = (n[top - 1] + SI_FAN - 1) / SI_FAN;
+      off[top] = at;
+      at += (n[top] * key_bytes + 127) / 128 * 128;
+    }
+    bytes = at;
+  }
+};
+
 // Optional per-launch event timing (lbsort_profile_enable).
 int prof_begin(hipStream_t s);
 void prof_end(int id, const char* name, hipStream_t s);

@@ -42,7 +42,8 @@ class Parts(ctypes.Structure):
 EXPORTS = ("lbsort_sort_keys", "lbsort_sort_pairs", "lbsort_sort_batch", "lbsort_local_sort",
            "lbsort_check", "lbsort_status_string", "lbsort_last_error", "lbsort_autotune",
            "lbsort_load_tuning", "lbsort_profile_enable", "lbsort_profile_read", "lbsort_search",
-           "lbsort_provenance", "lbsort_sort_pairs_noalloc", "lbsort_resolve_params")
+           "lbsort_provenance", "lbsort_sort_pairs_noalloc", "lbsort_resolve_params",
+           "lbsort_search_index_bytes", "lbsort_search_build_index", "lbsort_search_indexed")
 
 _lib = None
 
@@ -78,6 +79,10 @@ def load():
     lib.lbsort_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     lib.lbsort_search.argtypes = [i32, vp, u64, vp, u64, i32, vp, u32, vp, vp, vp]
     lib.lbsort_provenance.argtypes = [vp, u64, u64, u32, vp, vp, vp]
+    lib.lbsort_search_index_bytes.argtypes = [i32, u64]
+    lib.lbsort_search_index_bytes.restype = ctypes.c_uint64
+    lib.lbsort_search_build_index.argtypes = [i32, vp, u64, vp, vp]
+    lib.lbsort_search_indexed.argtypes = [i32, vp, u64, vp, vp, u64, i32, vp, u32, vp, vp, vp]
     lib.lbsort_sort_pairs_noalloc.argtypes = [i32, i32, vp, vp, vp, vp, u64, pp, pa, vp, vp]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
@@ -254,6 +259,40 @@ def search(sorted_keys: torch.Tensor, queries: torch.Tensor, upper: bool = False
     _check(lib.lbsort_search(kc, _ptr(sorted_keys), sorted_keys.numel(), _ptr(queries), nq, 1 if upper else 0,
                              _ptr(part_offsets), P, _ptr(pos), _ptr(part), _stream()))
     return pos, part
+
+
+class SearchIndex:
+    """lbsort_search_build_index over sorted_keys (device tensor): the index
+    lives in a device buffer of this object and stays valid while
+    sorted_keys is unchanged; search() is lbsort_search_indexed."""
+
+    def __init__(self, sorted_keys: torch.Tensor):
+        lib = load()
+        self.keys = sorted_keys
+        self.kc = key_code(sorted_keys.dtype)
+        nbytes = int(lib.lbsort_search_index_bytes(self.kc, sorted_keys.numel()))
+        # torch's device allocations are 256-byte aligned
+        self.buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=sorted_keys.device)
+        self.nbytes = nbytes
+        _check(lib.lbsort_search_build_index(self.kc, _ptr(sorted_keys), sorted_keys.numel(),
+                                             _ptr(self.buf) if nbytes else None, _stream()))
+
+    def search(self, queries: torch.Tensor, upper: bool = False, part_offsets: torch.Tensor | None = None):
+        lib = load()
+        if queries.dtype != self.keys.dtype:
+            raise TypeError("queries must have the dtype of sorted_keys")
+        nq = queries.numel()
+        pos = torch.empty(nq, dtype=torch.int64, device=queries.device)
+        part = None
+        P = 0
+        if part_offsets is not None:
+            P = part_offsets.numel() - 1
+            part = torch.empty(nq, dtype=torch.uint32, device=queries.device)
+        _check(lib.lbsort_search_indexed(self.kc, _ptr(self.keys), self.keys.numel(),
+                                         _ptr(self.buf) if self.nbytes else None, _ptr(queries), nq,
+                                         1 if upper else 0, _ptr(part_offsets), P, _ptr(pos), _ptr(part),
+                                         _stream()))
+        return pos, part
 
 
 def provenance(src_index: torch.Tensor, n: int, P: int):

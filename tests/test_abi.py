@@ -150,6 +150,34 @@ def test_search_and_provenance_argument_checks(lib):
     assert lib.lbsort_provenance(p, 5, 10, 4, None, None, None) == L.ERR_INVALID_ARG
 
 
+def test_search_index_sizes_and_argument_checks(lib):
+    """Index bytes: levels of ceil(n_{l-1} / 16) keys up to the first of at
+    most 16, each rounded up to 128 bytes (written out here from that rule);
+    argument errors are found on the host before any device work."""
+    def want(n, kb):
+        tot, m = 0, n
+        while m > 16:
+            m = -(-m // 16)
+            tot += -(-(m * kb) // 128) * 128
+        return tot
+    for n in (0, 1, 16, 17, 256, 257, 4096, 65537, 1 << 28, 10 ** 9 + 7):
+        assert lib.lbsort_search_index_bytes(L.U64, n) == want(n, 8), n
+        assert lib.lbsort_search_index_bytes(L.F32, n) == want(n, 4), n
+    # 2^28 u64 keys: levels of 2^24, 2^20, 2^16, 2^12, 2^8 and 16 keys
+    assert lib.lbsort_search_index_bytes(L.U64, 1 << 28) == 8 * (2 ** 24 + 2 ** 20 + 2 ** 16 + 2 ** 12 + 256) + 128
+    assert lib.lbsort_search_index_bytes(9, 100) == 0
+    p = ctypes.c_void_p(1 << 20)
+    odd = ctypes.c_void_p((1 << 20) + 64)
+    assert lib.lbsort_search_build_index(L.U64, None, 16, None, None) == 0        # no index needed
+    assert lib.lbsort_search_build_index(9, p, 100, p, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_search_build_index(L.U64, p, 100, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_search_build_index(L.U64, p, 100, odd, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_search_indexed(L.U64, None, 0, None, None, 0, 0, None, 0, None, None, None) == 0
+    assert lib.lbsort_search_indexed(L.U64, p, 100, None, p, 5, 0, None, 0, p, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_search_indexed(L.U64, p, 100, p, p, 5, 2, None, 0, p, None, None) == L.ERR_INVALID_ARG
+    assert lib.lbsort_search_indexed(L.U64, p, 100, p, p, 5, 0, None, 4, p, p, None) == L.ERR_INVALID_ARG
+
+
 def test_resolve_params_defaults_and_explicit(lib):
     """Without a tuned entry (no device here) the defaults: F = 8 for P > 16,
     else the power of two reaching P (at most 16); merge tile 2048; radix tile

@@ -4,6 +4,8 @@ for bit on every output, and against the multi-pass handler: P from 2 to 64
 (powers of two and not), both tile capacities, ragged and tiny inputs, heavy
 duplicates in every investigator mode, all-equal, sorted and reverse inputs,
 and batches of uneven instances."""
+from types import SimpleNamespace
+
 import numpy as np
 import pytest
 
@@ -97,3 +99,29 @@ def test_one_pass_batch(ws, P):
         a, e = int(seg[b]), int(seg[b + 1])
         o = O.sample_sort(keys[a:e], vals[a:e], P, 32)
         compare(r, o, P, b=b, seg=(a, e))
+
+
+@pytest.mark.parametrize("handler", [L.HANDLER_PASSES, ONE])
+def test_batch_of_many_tiny_instances(ws, handler):
+    """Thousands of instances of 0 to 12 keys between a few large ones: the
+    256 consecutive samples (and sample slots) a workgroup looks up span
+    hundreds of blocks, many of them empty."""
+    rng = np.random.default_rng(11)
+    sizes = [int(x) for x in rng.integers(0, 13, size=3000)]
+    sizes[100], sizes[1500], sizes[2999] = 70_000, 9_000, 130_001
+    keys = np.concatenate([datagen.uniform_keys(n, seed=400 + i) if n else np.zeros(0, np.uint64)
+                           for i, n in enumerate(sizes)])
+    vals = np.concatenate([np.arange(n, dtype=np.uint32) for n in sizes])
+    seg = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    P = 8
+    r = L.sort_batch(to_dev(keys), to_dev(seg), P, vals=to_dev(vals), s=16, want_send=True, want_cuts=True,
+                     handler=handler, workspace=ws)
+    L.check(r.workspace)
+    # host copies once, not per instance
+    h = SimpleNamespace(**{f: (getattr(r, f).cpu() if getattr(r, f) is not None else None)
+                           for f in ("keys", "vals", "part_offsets", "part_counts", "splitters", "send_counts",
+                                     "cuts")})
+    for b in range(len(sizes)):
+        a, e = int(seg[b]), int(seg[b + 1])
+        o = O.sample_sort(keys[a:e], vals[a:e], P, 16)
+        compare(h, o, P, b=b, seg=(a, e))

@@ -159,6 +159,36 @@ def test_search_parity(ws, dt):
     assert not to_host(pos).any()
 
 
+@pytest.mark.parametrize("dt", [np.uint64, np.uint32, np.float64, np.int32])
+def test_search_indexed_parity(ws, dt):
+    """The indexed search against the oracle and the plain search, bit for
+    bit, at sizes around the index's level boundaries (16^k, 16^k + 1), with
+    runs of equal keys that cross the 16-key groups, the extremes and keys
+    outside the data."""
+    rng = np.random.default_rng(31)
+    for n in (0, 1, 15, 16, 17, 255, 256, 257, 4096, 4097, 65_537, 300_007):
+        if dt in (np.uint64, np.uint32):
+            keys = datagen.uniform_keys(n, seed=32 + n, dtype=dt)
+        else:
+            keys = datagen.typed_keys(n, seed=32 + n, dtype=dt)
+        if n > 40:
+            keys[5:40] = keys[3]          # a run of equal keys longer than a group
+        sk = np.sort(keys) if dt in (np.uint64, np.uint32) else keys[np.argsort(T.comparable(keys), kind="stable")]
+        P = 4
+        G = np.array([i * n // P for i in range(P + 1)], dtype=np.uint64)
+        qr = datagen.uniform_keys(300, seed=33, dtype=np.uint64).view(np.uint8)[: 300 * keys.itemsize].view(keys.dtype)
+        q = np.concatenate([sk[rng.integers(0, n, 700)] if n else sk[:0], sk[:1], sk[-1:], sk[3:4], qr])
+        dk = to_dev(sk)
+        idx = L.SearchIndex(dk)
+        for upper in (False, True):
+            pos, part = idx.search(to_dev(q), upper, to_dev(G))
+            want_pos, want_part = T.search(sk, q, upper, G)
+            assert_same(f"pos n={n}", to_host(pos).view(np.uint64), want_pos)
+            assert_same(f"part n={n}", to_host(part), want_part)
+            p2, _ = L.search(dk, to_dev(q), upper)
+            assert_same(f"plain n={n}", to_host(p2), to_host(pos))
+
+
 def test_provenance_parity(ws):
     for n, P in ((1_000_003, 64), (77, 10), (5, 8)):
         keys = datagen.typed_keys(n, seed=30, dtype=np.float64)
