@@ -125,3 +125,31 @@ def test_batch_of_many_tiny_instances(ws, handler):
         a, e = int(seg[b]), int(seg[b + 1])
         o = O.sample_sort(keys[a:e], vals[a:e], P, 16)
         compare(h, o, P, b=b, seg=(a, e))
+
+
+@pytest.mark.parametrize("case", ["below_2_40", "medium_groups", "clustered_f64", "u32_normal", "u32_index"])
+def test_one_pass_after_every_local_sort_path(ws, case):
+    """The one-pass handler behind every branch of the local sort: blocks
+    that fall back to the full LSD passes (keys below 2^40), groups for the
+    mid-size sort (1000 top values; clustered doubles), and 32-bit keys
+    (radix passes only; generated index values)."""
+    n, P, vals = 1_000_000, 8, None
+    if case == "below_2_40":
+        keys = datagen.uniform_keys(n, seed=51) >> np.uint64(24)
+    elif case == "medium_groups":
+        low = datagen.uniform_keys(n, seed=52) >> np.uint64(24)
+        top = np.arange(7, 7007, 7, dtype=np.uint64)[datagen.uniform_keys(n, seed=53) % np.uint64(1000)]
+        keys = (top << np.uint64(40)) | low
+    elif case == "clustered_f64":
+        n, P = 2_000_000, 13
+        x = datagen.typed_keys(n, seed=54, dtype=np.float64).view(np.uint64)
+        keys = np.where(x >> np.uint64(63) == 1, ~x, x | np.uint64(1 << 63))
+    elif case == "u32_normal":
+        keys = datagen.normal_u32(n, seed=55)
+        P = 37
+    else:
+        keys = datagen.uniform_keys(n, seed=56, dtype=np.uint32)
+    vals = datagen.index_values(n)
+    check_case(keys, vals, P, 0, ws=ws, handler=ONE)
+    if case == "u32_index":
+        check_case(keys, None, P, 0, ws=ws, handler=ONE)
