@@ -160,21 +160,29 @@ __global__ __launch_bounds__(1024) void k_investigate(Plan p, u64* __restrict__ 
   const u32 b = blockIdx.x;
   const u32 P = p.P, per = P - 1;
   const u64 N = p.seg[b + 1] - p.seg[b];
+  // the loops over the P blocks take 8 blocks at a time, loads before
+  // stores, so that 8 loads are in flight rather than one
   u64* cuts = p.cuts + (u64)b * P * (P + 1);
   const u64* lo = p.lo + (u64)b * P * per;
   const u64* hi = p.hi + (u64)b * P * per;
   const K* v = (const K*)p.splitters + (u64)b * per;
   const u32 blk0 = b * P;
   for (u32 k = threadIdx.x; k <= P; k += blockDim.x) {
-    for (u32 i = 0; i < P; ++i) {
-      u64 c;
-      if (k == 0) {
-        c = 0;
-      } else if (k == P) {
-        c = p.blk_start[blk0 + i + 1] - p.blk_start[blk0 + i];
-      } else if (p.inv == 1) {
-        c = lo[(u64)i * per + k - 1];
-      } else if (p.inv == 2) {
+    if (k == 0 || k == P || p.inv == 1) {
+      // column 0 (zero), column P (the block sizes), NONE (the lower bounds)
+      for (u32 i0 = 0; i0 < P; i0 += 8) {
+        u64 c[8];
+#pragma unroll
+        for (u32 u = 0; u < 8; ++u) {
+          const u32 i = i0 + u < P ? i0 + u : P - 1;
+          c[u] = k == 0 ? 0 : (k == P ? p.blk_start[blk0 + i + 1] - p.blk_start[blk0 + i] : lo[(u64)i * per + k - 1]);
+        }
+#pragma unroll
+        for (u32 u = 0; u < 8; ++u)
+          if (i0 + u < P) cuts[(u64)(i0 + u) * (P + 1) + k] = c[u];
+      }
+    } else if (p.inv == 2) {
+      for (u32 i = 0; i < P; ++i) {
         // run of equal splitters containing k: [k0, k0 + d)
         u32 k0 = k;
         while (k0 > 1 && v[k0 - 2] == v[k - 1]) --k0;
@@ -182,26 +190,37 @@ __global__ __launch_bounds__(1024) void k_investigate(Plan p, u64* __restrict__ 
         while (k0 + d < P && v[k0 + d - 1] == v[k0 - 1]) ++d;
         const u64 base = lo[(u64)i * per + k0 - 1];
         const u64 m = hi[(u64)i * per + k0 - 1] - base;
-        c = d == 1 ? base : base + ((u64)(k - k0 + 1) * m) / (d + 1);
-      } else {
-        c = 0;  // COUNT: filled below
+        cuts[(u64)i * (P + 1) + k] = d == 1 ? base : base + ((u64)(k - k0 + 1) * m) / (d + 1);
       }
-      if (k == 0 || k == P || p.inv != 0) cuts[(u64)i * (P + 1) + k] = c;
     }
     if (k > 0 && k < P && p.inv == 0) {
       u64 L = 0, H = 0;
+#pragma unroll 8
       for (u32 i = 0; i < P; ++i) {
         L += lo[(u64)i * per + k - 1];
         H += hi[(u64)i * per + k - 1];
       }
-      const u64 T = (u64)(((unsigned __int128)k * N) / P);
+      // k <= P <= 1024: below 2^53 keys k N fits 64 bits
+      const u64 T = N < (1ull << 53) ? (u64)k * N / P : (u64)(((unsigned __int128)k * N) / P);
       const u64 Gk = T < L ? L : (T > H ? H : T);
       u64 extra = Gk - L;
-      for (u32 i = 0; i < P; ++i) {
-        const u64 l = lo[(u64)i * per + k - 1], m = hi[(u64)i * per + k - 1] - l;
-        const u64 take = m < extra ? m : extra;
-        extra -= take;
-        cuts[(u64)i * (P + 1) + k] = l + take;
+      for (u32 i0 = 0; i0 < P; i0 += 8) {
+        // a chunk's loads first, then its stores
+        u64 l[8], h[8];
+#pragma unroll
+        for (u32 u = 0; u < 8; ++u) {
+          const u32 i = i0 + u < P ? i0 + u : P - 1;
+          l[u] = lo[(u64)i * per + k - 1];
+          h[u] = hi[(u64)i * per + k - 1];
+        }
+#pragma unroll
+        for (u32 u = 0; u < 8; ++u) {
+          if (i0 + u >= P) break;
+          const u64 m = h[u] - l[u];
+          const u64 take = m < extra ? m : extra;
+          extra -= take;
+          cuts[(u64)(i0 + u) * (P + 1) + k] = l[u] + take;
+        }
       }
     }
   }
@@ -211,6 +230,7 @@ __global__ __launch_bounds__(1024) void k_investigate(Plan p, u64* __restrict__ 
   u64* Db = p.Dm + (u64)b * (P + 1) * P;
   for (u32 k = threadIdx.x; k <= P; k += blockDim.x) {
     u64 g = 0;
+#pragma unroll 8
     for (u32 i = 0; i < P; ++i) g += cuts[(u64)i * (P + 1) + k];
     Gb[k] = g;
     out_offsets[(u64)b * (P + 1) + k] = g;
@@ -218,11 +238,22 @@ __global__ __launch_bounds__(1024) void k_investigate(Plan p, u64* __restrict__ 
   __syncthreads();
   for (u32 k = threadIdx.x; k < P; k += blockDim.x) {
     u64 acc = Gb[k];
-    for (u32 i = 0; i < P; ++i) {
-      const u64 c = cuts[(u64)i * (P + 1) + k + 1] - cuts[(u64)i * (P + 1) + k];
-      Db[(u64)i * P + k] = acc;
-      acc += c;
-      if (out_send) out_send[(u64)b * P * P + (u64)i * P + k] = c;
+    for (u32 i0 = 0; i0 < P; i0 += 8) {
+      // a chunk's loads first, then its stores
+      u64 c[8];
+#pragma unroll
+      for (u32 u = 0; u < 8; ++u) {
+        const u32 i = i0 + u < P ? i0 + u : P - 1;
+        c[u] = cuts[(u64)i * (P + 1) + k + 1] - cuts[(u64)i * (P + 1) + k];
+      }
+#pragma unroll
+      for (u32 u = 0; u < 8; ++u) {
+        if (i0 + u >= P) break;
+        const u32 i = i0 + u;
+        Db[(u64)i * P + k] = acc;
+        acc += c[u];
+        if (out_send) out_send[(u64)b * P * P + (u64)i * P + k] = c[u];
+      }
     }
     Db[(u64)P * P + k] = Gb[k + 1];
     if (out_counts) out_counts[(u64)b * P + k] = Gb[k + 1] - Gb[k];
