@@ -16,7 +16,6 @@
 namespace lbs {
 
 void launch_plan(const Plan& p, hipStream_t s);
-void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s);
 void launch_fill_set(const FillSet& f, hipStream_t s);
 template <typename K>
 void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo = 0);

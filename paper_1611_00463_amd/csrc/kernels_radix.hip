@@ -242,10 +242,6 @@ __global__ void k_fill_set(FillSet f) {
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < f.n[r]; i += stride) f.a[r][i] = f.v[r];
 }
 
-__global__ void k_fill32(u32* __restrict__ a, u64 n, u32 v) {
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) a[i] = v;
-}
-
 // ----------------------------------------------------------------- histogram
 // Digit counts of all passes for the tiles of large blocks, accumulated per
 // block.  A workgroup covers `tpw` consecutive tiles (block-contiguous
@@ -1545,13 +1541,6 @@ void launch_fill_set(const FillSet& f, hipStream_t s) {
   u64 blocks = (most + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_fill_set, dim3((u32)blocks), dim3(256), 0, s, f); prof_end(pe_, "fill", s); }
-}
-
-void launch_fill32(u32* a, u64 n, u32 v, hipStream_t s) {
-  if (n == 0) return;
-  u64 blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  { const int pe_ = prof_begin(s); hipLaunchKernelGGL(k_fill32, dim3((u32)blocks), dim3(256), 0, s, a, n, v); prof_end(pe_, "fill", s); }
 }
 
 template <typename K>
