@@ -171,7 +171,7 @@ int lbsort_sort_pairs(int key_type, int val_type, const void *keys_in, const voi
  * Limit: a problem whose workspace (as lbsort_sort_pairs would size it)
  * exceeds LBSORT_NOALLOC_SCRATCH_BYTES returns LBSORT_ERR_UNSUPPORTED before
  * anything is enqueued; that is about 5.3 million 64-bit keys with values
- * (4.6 million with LBSORT_HANDLER_ONE_PASS at P = 64), or 7.9 million
+ * (4.4 million with LBSORT_HANDLER_ONE_PASS at P = 64), or 7.9 million
  * 32-bit keys with values.
  *
  * All calls on one device share that device's array and each call starts

@@ -142,7 +142,8 @@ struct Layout {
       splitters, mtile, rec_start, rec_end, rec_out, rec_n, slot_grp, grp_run, grp_out, tmpk, tmpv, seg, total;
   // one-pass handler
   u64 sseg, sbs, scuts, sDm, gsbase, ntile, skeys[2], svals[2], s_mtile, s_rec_start, s_rec_end, s_rec_out, s_rec_n,
-      s_slot_grp, s_grp_run, s_grp_out;
+      s_slot_grp, s_grp_run, s_grp_out, bsamp;
+  bool bsamp_on;
 };
 
 // Entries of the mid-size group list: groups of more than GF_HALO keys in the
@@ -216,6 +217,9 @@ static Layout make_layout(const Shape& sh) {
   l.s_slot_grp = take(one ? (sh.s_mtiles + sh.s_ng0 + 1) * 4 : 0);
   l.s_grp_run = take(one ? (u64)sh.s_ng0 * sh.s_F * 16 : 0);
   l.s_grp_out = take(one ? (u64)sh.s_ng0 * 16 : 0);
+  // block samples: ceil(n_i / m) keys of block i at floor(start_i / m) + i
+  l.bsamp_on = one && K == 8 && hybrid_local_sort();
+  l.bsamp = take(l.bsamp_on ? (sh.total_n / SAMP_STRIDE + NB + 1) * K : 0);
   l.total = o;
   return l;
 }
@@ -345,11 +349,12 @@ static int make_shape(int key_type, int val_type, u32 B, u64 total_n, const lbso
   sh.s_F = sh.s_TM = sh.s_L = sh.s_ng0 = sh.q = 0;
   sh.s_mtiles = 0;
   if (sh.handler == LBSORT_HANDLER_ONE_PASS && sh.L > 0) {
-    // every run (B P^2 of them) adds at most one sample above len / m
+    // every run (B P^2 of them) adds at most two samples above len / m
+    // (its first element, and the block positions that are multiples of m)
     const u64 PP = (u64)p.P * p.P;
-    sh.s_max = total_n / SAMP_STRIDE + (u64)B * (PP + 1) + 1;
+    sh.s_max = total_n / SAMP_STRIDE + (u64)B * (2 * PP + 1) + 1;
     sh.q = sh.TM / SAMP_STRIDE - p.P;
-    sh.mtiles = (total_n / SAMP_STRIDE + B * PP) / sh.q + NB + 1;
+    sh.mtiles = (total_n / SAMP_STRIDE + 2 * B * PP) / sh.q + NB + 1;
     sh.s_F = pow2P < 16 ? pow2P : 16;
     if (p.P > 16) sh.s_F = 8;
     sh.s_TM = 2048;
@@ -413,6 +418,9 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   p.grp_out = (u64*)(ws + lay.grp_out);
   p.ng_max = sh.ng0;
   p.mtiles_max = (u32)sh.mtiles;
+  // block samples where the local sort's last writer is the group fix-up
+  // (64-bit keys on the fix-up path), which writes blocks in position order
+  if (lay.bsamp_on) p.bsamp = ws + lay.bsamp;
   p.vidx = sh.val_type == LBSORT_VAL_INDEX;
   if (seg_in) {
     p.seg = seg_in;
@@ -456,6 +464,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   launch_plan(p, st);
   // the fix-up path's top-digit passes leave out a digit that no block needs
   Plan ph = px;
+  ph.bsamp = nullptr;  // the top-digit passes do not write the local sort's output
   if (hybrid) {
     ph.run_slot = C_RUN_TOP;
     ph.run_mask = 0xE0u;  // digits 5, 6, 7

@@ -475,6 +475,7 @@ __global__ __launch_bounds__(256) void k_presorted(Plan p, const K* __restrict__
         }
         dst[o] = k;
         if (HASV) dstv[o] = vv[u];
+        block_sample<K>(p, blk, bs, o, k);
       }
     }
   }
@@ -607,11 +608,14 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
   u32* dstv = dstv0;
   u64 kx_top = p.kx_top, kx_fm = p.kx_fm;  // applied to keys read from the input only
   if (REDO && p.counters[C_NLARGE] == 0) return;
+  // the last pass writes the local sort's output: its block samples too
+  bool emit = p.bsamp != nullptr && pass + 1 == p.D;
   if (p.run_slot) {
     u32 run = p.counters[p.run_slot] & p.run_mask;
     if (run == 0) run = 1u << (31 - __clz(p.run_mask));  // at least one pass writes pass_out
     if (((run >> pass) & 1u) == 0) return;
     const u32 a = (u32)__popc(run & ((1u << pass) - 1u)), e = (u32)__popc(run);
+    emit = p.bsamp != nullptr && a + 1 == e;
     // the k-th pass that runs writes pass_out when e - 1 - k is even
     const bool to_out = ((e - 1u - a) & 1u) == 0;
     dst = (K*)(to_out ? p.pass_out : p.pass_tmp);
@@ -820,6 +824,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
           if ((u32)(c + j) * NT + tid < tile_n) {
             dblk[oc[j]] = ok[j];
             if (HASV && !SPLITV) vblk[oc[j]] = ov[j];
+            if (emit) block_sample<K>(p, blk, bstart, bstart + oc[j], ok[j]);
           }
       }
       if (SPLITV) {
@@ -967,6 +972,7 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix(Plan p, const u64* __restr
     }
     dst[ws + o] = key;
     if (HASV) dstv[ws + o] = v[k];
+    block_sample<u64>(p, blk, bs, ws + o, key);
   }
   // one store per wave that found a mixed large group
   if (__ballot(bad) != 0 && lane == 0) {
@@ -1246,6 +1252,7 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix_mid(Plan p, const u64* __r
     if (place[k] != NONE) {
       dst[xs + place[k]] = s_k[w];
       if (HASV) dstv[xs + place[k]] = v[k];
+      block_sample<u64>(p, blk, bs, xs + place[k], s_k[w]);
     }
   }
   if (__ballot(bad) != 0 && lane == 0) p.gflags2[blk] = 1u;
@@ -1299,6 +1306,14 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
     const u64 g0 = ent & ((1ull << 44) - 1);
     const u32 len = (u32)(ent >> 44) < GF_MID ? (u32)(ent >> 44) : GF_MID;
     const int nj = (int)((len + 63) / 64);
+    // the group's block (for its block samples): the last block starting at
+    // or before g0 (a group lies inside one non-empty block)
+    u32 gblk = 0;
+    u64 gbs = 0;
+    if (p.bsamp) {
+      gblk = find_seg(p.blk_start, p.NB, g0);
+      gbs = p.blk_start[gblk];
+    }
     u64 keys[GM_ITEMS];
     u32 vals[HASV ? GM_ITEMS : 1];
 #pragma unroll
@@ -1414,6 +1429,7 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
           }
           dst[g0 + r] = keys[j];
           if (HASV) dstv[g0 + r] = vals[j];
+          block_sample<u64>(p, gblk, gbs, g0 + r, keys[j]);
         }
       }
       continue;
@@ -1424,6 +1440,7 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
       if (idx < len) {
         dst[g0 + idx] = keys[j];
         if (HASV) dstv[g0 + idx] = vals[j];
+        block_sample<u64>(p, gblk, gbs, g0 + idx, keys[j]);
       }
     }
   }
@@ -1521,6 +1538,7 @@ __global__ __launch_bounds__(SORT_NT) void k_small_sort(Plan p, const K* __restr
   for (u32 i = tid; i < n; i += SORT_NT) {
     dst[bstart + i] = s_keys[i];
     if (HASV) dstv[bstart + i] = s_vals[i];
+    block_sample<K>(p, blk, bstart, bstart + i, s_keys[i]);
   }
 }
 

@@ -2,24 +2,33 @@
 // received at once (F = the power of two reaching P), with tile boundaries
 // chosen the way the paper chooses its splitters, by regular sampling.
 //
-// Every run (block i's slice for partition k) offers the elements at its
-// positions 0, m, 2m, ... as samples.  The samples of block i, taken run by
-// run, are a sorted sequence, and the sample runs of partition k are exactly
-// the structure of the main problem at 1/m of its size: they are merged per
-// partition by the multi-pass handler (exact merge-path tiles), which orders
-// them by (key, run, position), the order of the stable merge.
+// Every run (block i's slice for partition k) offers as samples the elements
+// at its positions 0, m, 2m, ...; or, where the local sort writes block
+// samples (64-bit keys: the group fix-up writes its blocks in position
+// order, so writing the keys at block positions that are multiples of m to a
+// side array costs little there, while a radix pass would scatter them), its
+// first element and the elements at the block positions after it that are
+// multiples of m, read from that side array: about 1/m of the keys instead of
+// a strided read that touches every cache line.  Either way consecutive
+// samples of a run, and the last one and the run's end, are at most m apart.  The samples of block i, taken run by run, are a sorted
+// sequence, and the sample runs of partition k have the structure of the
+// main problem at about 1/m of its size: they are merged per partition by
+// the multi-pass handler (exact merge-path tiles), which orders them by
+// (key, run, position), the order of the stable merge.
 //
 // Tile j of partition k spans from the sample of sorted rank j*q to the one of
 // rank (j+1)*q (the first tile starts at the partition's start, the last ends
 // at its end).  A boundary b that is a sample cuts run i at the number of its
 // elements that precede b in that order: elements <= b's key for runs before
 // b's own run, < b's key for runs after it, and b's position in its own run.
-// If s_i samples of run i precede b, that count lies in (m(s_i - 1), m s_i];
-// summed over the runs, a boundary's rank lies in (m S - P m, m S] when S
-// samples precede it, so a tile holds fewer than m q + P m elements whatever
-// the keys (heavy duplicates included): q is chosen so that this is the
-// merge tile's capacity.  No selection rounds are needed: one binary search
-// per run and boundary.
+// If samples 0 .. s-1 of run i (at run positions p_0 = 0 < p_1 < ...) precede
+// b and sample s does not, that count lies in (p_{s-1}, p_s] (p_s = the run's
+// length past its last sample; 0 when s = 0).  Between two boundaries with q
+// samples between them a run gains at most p_{s'} - p_{s-1} <= m (s' - s + 1)
+// elements, so a tile holds at most m q + P m elements whatever the keys
+// (heavy duplicates included): q is chosen so that this is the merge tile's
+// capacity.  No selection rounds are needed: one binary search per run and
+// boundary.
 #include "lbsort_internal.hpp"
 
 namespace lbs {
@@ -39,9 +48,14 @@ __global__ __launch_bounds__(256) void k_samp_meta(Plan p, SampPlan sp) {
   const u32 P = p.P, m = sp.m;
   const u64* c = p.cuts + (u64)b * P * (P + 1);
   for (u32 x = tid; x < P * P; x += 256) {
+    // run (i, k) = block positions [c0, c0 + C): its first element and the
+    // multiples of m after it
     const u32 i = x / P, k = x % P;
-    const u64 C = c[(u64)i * (P + 1) + k + 1] - c[(u64)i * (P + 1) + k];
-    s_ns[x] = (u32)((C + m - 1) / m);
+    const u64 c0 = c[(u64)i * (P + 1) + k], C = c[(u64)i * (P + 1) + k + 1] - c0;
+    if (p.bsamp)
+      s_ns[x] = C ? (u32)(1 + (c0 + C - 1) / m - c0 / m) : 0u;
+    else
+      s_ns[x] = (u32)((C + m - 1) / m);  // run positions 0, m, 2m, ...
   }
   __syncthreads();
   u64* sc = sp.scuts + (u64)b * P * (P + 1);
@@ -60,7 +74,7 @@ __global__ __launch_bounds__(256) void k_samp_meta(Plan p, SampPlan sp) {
     s_G[k + 1] = col;
   }
   __syncthreads();
-  const u64 PP1 = (u64)P * P + 1;
+  const u64 PP1 = 2 * (u64)P * P + 1;
   const u64 base = p.blk_start[(u64)b * P] / m + (u64)b * PP1;
   if (tid == 0) {
     sp.sseg[b] = base;
@@ -118,10 +132,24 @@ __global__ __launch_bounds__(256) void k_samp_gather(Plan p, SampPlan sp, const 
     }
     k = lo;
   }
+  // sample j of the run: its first element (j = 0), else the j-th block
+  // position after it that is a multiple of m, whose key the local sort
+  // wrote to the block samples
   const u64 j = off - sc[k];
-  const u64 at = p.blk_start[bi] + p.cuts[(u64)bi * (P + 1) + k] + j * sp.m;
-  skeys[u] = sorted[at];
-  svals[u] = (u32)at;
+  const u64 bs = p.blk_start[bi], c0 = p.cuts[(u64)bi * (P + 1) + k];
+  if (!p.bsamp) {
+    // no block samples: the run's elements at run positions 0, m, 2m, ...
+    const u64 at = bs + c0 + j * sp.m;
+    skeys[u] = sorted[at];
+    svals[u] = (u32)at;
+  } else if (j == 0) {
+    skeys[u] = sorted[bs + c0];
+    svals[u] = (u32)(bs + c0);
+  } else {
+    const u64 xm = c0 / sp.m + j;  // block position / m
+    skeys[u] = ((const K*)p.bsamp)[bs / sp.m + bi + xm];
+    svals[u] = (u32)(bs + xm * sp.m);
+  }
 }
 
 // Prefix of the merge tiles over the partitions of all instances (one

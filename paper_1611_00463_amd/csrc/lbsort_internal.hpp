@@ -140,6 +140,12 @@ struct Plan {
   u32* pass_outv;
   void* pass_tmp;
   u32* pass_tmpv;
+  // Block samples for the one-pass handler (null otherwise): every kernel
+  // that writes the local sort's final output also writes the key at each
+  // block position x = 0, m, 2m, ... to bsamp[floor(bstart / m) + block +
+  // x / m] (block_sample), so that the handler's samples need no strided
+  // read of the sorted blocks.
+  void* bsamp;
 };
 
 // The one-pass handler's sample problem (kernels_sampled.hip): the samples of
@@ -306,6 +312,14 @@ struct TileQueue {
 };
 
 // Ranges of 32-bit words to set in one launch.
+// The block sample of a key written to global position g of block blk
+// (starting at bs): kept when g - bs is a multiple of SAMP_STRIDE.
+template <typename K>
+__device__ inline void block_sample(const Plan& p, u32 blk, u64 bs, u64 g, K key) {
+  const u64 x = g - bs;
+  if (p.bsamp && (x % SAMP_STRIDE) == 0) ((K*)p.bsamp)[bs / SAMP_STRIDE + blk + x / SAMP_STRIDE] = key;
+}
+
 constexpr int FILL_MAX = 6;
 struct FillSet {
   u32* a[FILL_MAX];
