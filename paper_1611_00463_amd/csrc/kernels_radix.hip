@@ -525,18 +525,22 @@ __device__ inline void rank_items(const K (&keys)[ITEMS], u32 wbase, u32 tile_n,
     const u32 d = (u32)(keys[j] >> shift) & (RADIX - 1);
     // Peers: lanes whose digit equals this lane's.  For every digit bit the
     // lane's bit is spread to a full-word mask t (signed one-bit extract);
-    // t ^ ballot marks the lanes whose bit differs, one 32-bit half at a time,
-    // and the peers are the valid lanes marked by no bit.
+    // t ^ ballot marks the lanes whose bit differs, and each 32-bit half of
+    // the peer set keeps the lanes marked by no bit: plo &= ~(t ^ ballot), one
+    // three-input bit operation (truth table 0x90) per half and bit.  The
+    // empty asm keeps t opaque, so that the ballot tests t itself instead of
+    // a second shift of the digit.
     const u64 vm = __ballot(valid);
-    u32 xlo = 0, xhi = 0;
+    u32 plo = (u32)vm, phi = (u32)(vm >> 32);
 #pragma unroll
     for (int b = 0; b < RADIX_BITS; ++b) {
-      const u32 t = (u32)__builtin_amdgcn_sbfe((int)d, b, 1);
+      u32 t = (u32)__builtin_amdgcn_sbfe((int)d, b, 1);
+      asm("" : "+v"(t));
       const u64 bb = __ballot(t != 0u);
-      xlo |= t ^ (u32)bb;
-      xhi |= t ^ (u32)(bb >> 32);
+      plo = __builtin_amdgcn_bitop3_b32(plo, t, (u32)bb, 0x90);
+      phi = __builtin_amdgcn_bitop3_b32(phi, t, (u32)(bb >> 32), 0x90);
     }
-    const u64 m = ((u64)((u32)(vm >> 32) & ~xhi) << 32) | ((u32)vm & ~xlo);
+    const u64 m = ((u64)phi << 32) | plo;
     const u32 below = count_below(m);
     u32 base = 0;
     if (valid) base = wc[d];
