@@ -666,15 +666,22 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
       K keys[ITEMS];
       u32 vals[HASV && !SPLITV ? ITEMS : 1];
       if (!HASV || SPLITV || srcv != nullptr) {
+        // The keys' loads first, then the values'.  Every load is issued (a
+        // lane past the tile reads the tile's first element, which it never
+        // uses: its ranking, staging and writes are masked), so that the
+        // compiler knows how many loads follow each one and item j waits for
+        // keys[j] alone; a load skipped by a branch would make the ranking
+        // wait for all of them.
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
           const u32 idx = wbase + j * 64 + lane;
-          if (idx < tile_n) {
-            keys[j] = src[tbase + idx];
-            if (HASV && !SPLITV) vals[j] = srcv[tbase + idx];
-          } else {
-            keys[j] = 0;
-            if (HASV && !SPLITV) vals[j] = 0;
+          keys[j] = src[tbase + (idx < tile_n ? idx : 0u)];
+        }
+        if (HASV && !SPLITV) {
+#pragma unroll
+          for (int j = 0; j < ITEMS; ++j) {
+            const u32 idx = wbase + j * 64 + lane;
+            vals[j] = srcv[tbase + (idx < tile_n ? idx : 0u)];
           }
         }
       } else {
@@ -685,7 +692,7 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
           const u32 idx = wbase + j * 64 + lane;
-          keys[j] = idx < tile_n ? src[tbase + idx] : (K)0;
+          keys[j] = src[tbase + (idx < tile_n ? idx : 0u)];
           if (HASV && !SPLITV) vals[j] = (u32)(vgen + idx);
         }
       }
