@@ -419,7 +419,12 @@ __global__ __launch_bounds__(256) void k_presorted(Plan p, const K* __restrict__
   const u32 ntiles = p.tstart[p.NB];
   const u32 t0 = blockIdx.x * PRESORTED_TPW;
   if (t0 >= ntiles) return;
-  if (tid == 0) s_blk = find_seg(p.tstart, p.NB, t0);
+  // one workgroup per tile: the block by a wave-wide search (a batch has
+  // tens of thousands of blocks)
+  if (tid < 64) {
+    const u32 b = wave_find_seg(p.tstart, p.NB, t0);
+    if (tid == 0) s_blk = b;
+  }
   __syncthreads();
   u32 blk = s_blk;
   const u32 t1 = t0 + PRESORTED_TPW < ntiles ? t0 + PRESORTED_TPW : ntiles;
@@ -435,13 +440,16 @@ __global__ __launch_bounds__(256) void k_presorted(Plan p, const K* __restrict__
     for (u32 i0 = 0; i0 < tile_n; i0 += 256 * U) {
       K kk[U];
       u32 vv[U];
+      // every load issued (past the tile a lane reads the tile's first
+      // element and writes nothing), so that each store waits for its own
+      // element's loads only
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const u32 i = i0 + (u32)u * 256 + tid;
-        const u64 x = tbase + i;
-        kk[u] = i < tile_n ? src[x] : (K)0;
+        const u64 xc = tbase + (i < tile_n ? i : 0u);
+        kk[u] = src[xc];
         vv[u] = 0;
-        if (HASV && i < tile_n) vv[u] = srcv != nullptr ? srcv[x] : (u32)(vgen + (x - bs));
+        if (HASV) vv[u] = srcv != nullptr ? srcv[xc] : (u32)(vgen + (xc - bs));
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_samp_bounds(Plan p, SampPlan sp, const 
   const u32 lane = threadIdx.x & 63;
   const u32 P = p.P, F = p.F, NG = p.B * P;
   if (t >= p.mtile[NG]) return;
-  const u32 g = find_seg(p.mtile, NG, t);  // the partition holding tile t (empty ones skipped)
+  const u32 g = wave_find_seg(p.mtile, NG, t);  // the partition holding tile t (empty ones skipped)
   const u32 j = t - p.mtile[g], nt = p.mtile[g + 1] - p.mtile[g];
   const u32 b = g / P, k = g % P;
   u64 base = 0, len = 0;

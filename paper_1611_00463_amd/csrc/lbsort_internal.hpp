@@ -233,6 +233,26 @@ __device__ inline u32 find_seg(const T* prefix, u32 n, u64 t) {
   return lo;
 }
 
+// find_seg by a whole wave (all 64 lanes active, the same t in each): every
+// round the lanes probe 64 evenly spaced starts of the range [lo, hi) and one
+// ballot of the non-decreasing test narrows it to one step, so 32768
+// segments take 3 dependent loads instead of 15.
+template <typename T>
+__device__ inline u32 wave_find_seg(const T* prefix, u32 n, u64 t) {
+  const u32 lane = threadIdx.x & 63;
+  u32 lo = 0, hi = n;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    const u32 step = (hi - lo + 63) / 64;
+    const u32 pos = lo + (lane + 1) * step;  // < hi + 64 <= n + 64
+    const bool le = pos < hi && (u64)prefix[pos] <= t;
+    const u32 c = (u32)__popcll(__ballot(le));  // the probes at or before the answer
+    const u32 nhi = lo + (c + 1) * step;
+    lo += c * step;
+    hi = nhi < hi ? nhi : hi;
+  }
+  return lo;
+}
+
 // x of lane `l` (the same l in every lane), read without LDS.
 __device__ inline u32 lane_value(u32 x, int l) { return (u32)__builtin_amdgcn_readlane((int)x, l); }
 __device__ inline u64 lane_value(u64 x, int l) {
