@@ -371,6 +371,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
                const u64* seg_in, const lbsort_parts* parts, char* ws, hipStream_t st) {
   Plan p;
   memset(&p, 0, sizeof p);
+  p.gshift = sh.key_type == LBSORT_F64 ? 32u : 40u;
   p.B = sh.B;
   p.P = sh.P;
   p.NB = sh.B * sh.P;
@@ -444,8 +445,12 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   auto dk = [&](u32 j) -> K* { return ((S - 1 - j) % 2 == 0) ? kout : tk; };
   auto dv = [&](u32 j) -> u32* { return ((S - 1 - j) % 2 == 0) ? vout : tv; };
 
-  // the fix-up path of 64-bit keys needs the counts of the three top digits only
+  // the fix-up path of 64-bit keys needs the counts of the top digits only:
+  // three, or four for doubles (their sign and exponent leave few distinct
+  // values in the top 24 bits, so groups of equal top 24 bits run to
+  // hundreds of keys; one more pass is cheaper than the mid-size group sort)
   const bool hybrid = sizeof(K) == 8 && hybrid_local_sort();
+  const u32 ntop = (64u - p.gshift) / RADIX_BITS;
   {
     // every word that must start at a known value, in one launch
     FillSet f;
@@ -467,7 +472,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   ph.bsamp = nullptr;  // the top-digit passes do not write the local sort's output
   if (hybrid) {
     ph.run_slot = C_RUN_TOP;
-    ph.run_mask = 0xE0u;  // digits 5, 6, 7
+    ph.run_mask = ntop == 4 ? 0xF0u : 0xE0u;  // digits 4 (doubles), 5, 6, 7
   }
   if (sh.has_large) {
     // the histogram also finds the large blocks that are already in order
@@ -476,7 +481,7 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
     const bool detect = sh.presort == LBSORT_PRESORTED_DETECT;
     Plan hp = hybrid ? ph : px;
     hp.presorted = detect ? presorted : nullptr;
-    launch_hist<K>(hp, kin, st, hybrid ? 5u : 0u);
+    launch_hist<K>(hp, kin, st, hybrid ? 8u - ntop : 0u);
     if (detect) {
       Plan cp = px;
       cp.presorted = presorted;
@@ -490,9 +495,10 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
   if (sh.has_large) {
     if constexpr (sizeof(K) == 8) {
       if (hybrid) {
-        // 64-bit keys: the three highest digits first (blocks grouped by their
-        // top 24 bits), then the group fix-up into the step-1 output F; the
-        // blocks it flags are sorted again over all eight digits.
+        // 64-bit keys: the three highest digits first (four for doubles:
+        // blocks grouped by key >> gshift), then the group fix-up into the
+        // step-1 output F; the blocks it flags are sorted again over all eight
+        // digits.
         K* const F = dk(sh.D - 1);
         u32* const FV = dv(sh.D - 1);
         K* const O = F == kout ? tk : kout;
@@ -502,13 +508,13 @@ static int run(const Shape& sh, const Layout& lay, const K* kin, const u32* vin,
         ph.pass_outv = OV;
         ph.pass_tmp = F;
         ph.pass_tmpv = FV;
-        for (u32 j = 5; j < 8; ++j) launch_onesweep<K, HASV>(ph, kin, vin, O, OV, j, st);
+        for (u32 j = 8 - ntop; j < 8; ++j) launch_onesweep<K, HASV>(ph, kin, vin, O, OV, j, st);
         launch_group_fix<HASV>(p, (const u64*)O, OV, (u64*)F, FV, st);
         launch_group_fix_mid<HASV>(p, (const u64*)O, OV, (u64*)F, FV, st);
         launch_group_mid<HASV>(p, (const u64*)O, OV, (u64*)F, FV, device_cus() * 8, st);
         Plan q = p;
         q.only = p.gflags2;
-        q.epoch_base = 8;  // the status words of the passes above stay valid for epochs 6..8
+        q.epoch_base = 8;  // the status words of the passes above stay valid for epochs 5..8
         {
           FillSet f;
           f.add(p.counters + C_TICKET, NQ * sh.D, 0);

@@ -879,8 +879,9 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
 
 // ----------------------------------------------------------------- group fix-up
 // Second phase of the local sort of 64-bit keys.  The large blocks arrive
-// stably sorted by their top 24 bits (radix passes over the three highest
-// digits); a group is a run of keys with equal top bits, and each group must
+// stably sorted by key >> p.gshift (radix passes over the three highest
+// digits, the four highest for doubles); a group is a run of keys with equal
+// top bits, and each group must
 // end up sorted by the whole key, stably.  One workgroup per tile of a large
 // block, with a window of GF_HALO keys on either side in LDS:
 //  * a group of at most GF_HALO keys lies inside the window of every tile
@@ -889,7 +890,6 @@ __global__ __launch_bounds__(NT, MINW) void k_onesweep(Plan p, const K* __restri
 //  * a larger group keeps its order, which is right when all its keys are
 //    equal (heavy duplicates); a key of it that differs from its predecessor
 //    flags the block for k_group_fix_mid.
-constexpr u32 GF_SHIFT = 40;
 
 // The fix-ups work on parts of GF1_SPAN keys of a radix tile (rtile /
 // GF1_SPAN parts per tile), so that their LDS window is small enough for
@@ -922,6 +922,7 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix(Plan p, const u64* __restr
   const u64 we = be - te > GF_HALO ? te + GF_HALO : be;
   const u32 wn = (u32)(we - ws);
   const bool wfirst = ws == bs, wlast = we == be;
+  const u32 gsh = p.gshift;  // groups: equal key >> gsh
   // all loads issued at once: the window's keys (into LDS) and this thread's
   // values of the tile (kept in registers until the write)
   constexpr int KL = (GF1_WIN + GF1_NT - 1) / GF1_NT, VL = GF1_SPAN / GF1_NT;
@@ -955,7 +956,7 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix(Plan p, const u64* __restr
   for (u32 base = 0; base < wn + 1; base += GF1_NT) {
     const u32 w = base + tid;
     bool h = false;
-    if (w < wn) h = w == 0 ? wfirst : (s_k[w] >> GF_SHIFT) != (s_k[w - 1] >> GF_SHIFT);
+    if (w < wn) h = w == 0 ? wfirst : (s_k[w] >> gsh) != (s_k[w - 1] >> gsh);
     else if (w == wn) h = wlast;
     const u64 m = __ballot(h);
     if (lane == 0 && w < wn + 64) s_hb[w >> 6] = m;
@@ -1063,6 +1064,7 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix_mid(Plan p, const u64* __r
   const u64 ws = ts - bs > GF_HALO ? ts - GF_HALO : bs;
   const u64 we = be - te > GF_HALO ? te + GF_HALO : be;
   const u32 wn = (u32)(we - ws);
+  const u32 gsh = p.gshift;  // groups: equal key >> gsh (32 or 40)
   // all loads issued at once: the inner window's keys (into LDS) and this
   // thread's values of the tile (kept in registers until the write)
   constexpr int KL = (GF1_WIN + GF1_NT - 1) / GF1_NT, VL = GF1_SPAN / GF1_NT;
@@ -1096,8 +1098,8 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix_mid(Plan p, const u64* __r
   // only where the group at that edge of the tile runs to the edge of the
   // inner window (equal top bits there, since the keys are sorted by them);
   // elsewhere every group touching the tile starts and ends inside.
-  const bool need_l = ws > bs && (s_k[0] >> GF_SHIFT) == (s_k[o0] >> GF_SHIFT);
-  const bool need_r = we < be && (s_k[wn - 1] >> GF_SHIFT) == (s_k[o1 - 1] >> GF_SHIFT);
+  const bool need_l = ws > bs && (s_k[0] >> gsh) == (s_k[o0] >> gsh);
+  const bool need_r = we < be && (s_k[wn - 1] >> gsh) == (s_k[o1 - 1] >> gsh);
   const u64 xs = need_l ? (ts - bs > GF_MID ? ts - GF_MID : bs) : ws;
   const u64 xe = need_r ? (be - te > GF_MID ? te + GF_MID : be) : we;
   const u32 xn = (u32)(xe - xs);
@@ -1106,15 +1108,15 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix_mid(Plan p, const u64* __r
     // top bits of the outer halo: one position per thread and side
     static_assert(XH <= (u32)GF1_NT, "one outer-halo position per thread");
     const u32* const hi = reinterpret_cast<const u32*>(src) + 1;  // high words: hi[2 g]
-    if (tid < nl) s_xt[0][tid] = hi[2 * (xs + tid)] >> (GF_SHIFT - 32);
-    if (tid < nr) s_xt[1][tid] = hi[2 * (we + tid)] >> (GF_SHIFT - 32);
+    if (tid < nl) s_xt[0][tid] = hi[2 * (xs + tid)] >> (gsh - 32);
+    if (tid < nr) s_xt[1][tid] = hi[2 * (we + tid)] >> (gsh - 32);
     __syncthreads();
   }
   // top bits of outer-window position x
   auto top = [&](u32 x) -> u32 {
     if (x < nl) return s_xt[0][x];
     const u32 i = x - nl;
-    return i < wn ? (u32)(s_k[i] >> GF_SHIFT) : s_xt[1][i - wn];
+    return i < wn ? (u32)(s_k[i] >> gsh) : s_xt[1][i - wn];
   };
   // Position x starts a group when it is the block's first key or its top
   // bits differ from those at x - 1; the window's first position inside a
@@ -1130,7 +1132,7 @@ __global__ __launch_bounds__(GF1_NT) void k_group_fix_mid(Plan p, const u64* __r
     for (u32 base = 0; base < xn + 1; base += GF1_NT) {
       const u32 x = base + tid;
       bool h = false;
-      if (x < xn) h = x == 0 ? xfirst : (s_k[x] >> GF_SHIFT) != (s_k[x - 1] >> GF_SHIFT);
+      if (x < xn) h = x == 0 ? xfirst : (s_k[x] >> gsh) != (s_k[x - 1] >> gsh);
       else if (x == xn) h = xlast;
       const u64 m = __ballot(h);
       if (lane == 0 && x < xn + 64) {
@@ -1288,15 +1290,15 @@ template void launch_group_fix_mid<false>(const Plan&, const u64*, const u32*, u
 template void launch_group_fix_mid<true>(const Plan&, const u64*, const u32*, u64*, u32*, hipStream_t);
 
 // ----------------------------------------------------------------- mid-size groups
-// Groups of GF_HALO+1 .. GF_MID keys listed by k_group_fix.  Their top 24 bits
-// are equal, so a stable LSD sort over the five low digits finishes them.
+// Groups of GF_HALO+1 .. GF_MID keys listed by k_group_fix.  Their bits from
+// p.gshift up are equal, so a stable LSD sort over the digits below (five, or
+// four for doubles) finishes them.
 // Each wave takes whole groups (static stride over the list): the group sits
 // in registers (GM_ITEMS keys per lane), every pass ranks with the wave's own
 // digit counters and scatters through the wave's LDS slice.
 constexpr int GM_NT = 256;
 constexpr int GM_WAVES = GM_NT / 64;
 constexpr int GM_ITEMS = GF_MID / 64;
-constexpr int GM_DIGITS = GF_SHIFT / RADIX_BITS;
 
 // LDS accesses of one wave to its own slice, ordered across its lanes.
 __device__ inline void wave_lds_sync() {
@@ -1316,6 +1318,9 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
   const u32 lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const u64 nmid = p.counters[C_NMID] < p.mid_cap ? p.counters[C_NMID] : p.mid_cap;
   const u32 nw = gridDim.x * GM_WAVES;
+  // digits below the group shift (5, or 4 for doubles); after the pass over
+  // the highest of them, runs of equal key >> rsh remain
+  const u32 gd = p.gshift / RADIX_BITS, rsh = (gd - 1) * RADIX_BITS;
   u64* const sk = s_k[w];
   u32* const sv = s_v[w];
   u32* const sc = s_c[w];
@@ -1388,12 +1393,13 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
       }
       wave_lds_sync();
     };
-    // The top 24 bits are equal in a group.  One pass over digit 4 (bits
-    // 32..39) leaves runs of keys with equal bits 32..63, short for keys
-    // spread over the low 40 bits; a run of at most 64 keys is finished by
-    // ranking by (key, position).  If some run is longer, the five passes over
-    // digits 0..4 sort the group instead (stable from any starting order).
-    radix_pass(GM_DIGITS - 1);
+    // The bits from gshift up are equal in a group.  One pass over the digit
+    // below them (digit 4, bits 32..39, for gshift 40) leaves runs of keys
+    // with equal key >> rsh, short for keys spread over the low bits; a run
+    // of at most 64 keys is finished by ranking by (key, position).  If some
+    // run is longer, the passes over digits 0..gd-1 sort the group instead
+    // (stable from any starting order).
+    radix_pass(gd - 1);
 #pragma unroll
     for (int j = 0; j < GM_ITEMS; ++j) {
       if (j >= nj) break;
@@ -1406,7 +1412,7 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
     for (int j = 0; j <= GM_ITEMS; ++j) {
       if (j > nj) break;
       const u32 i = j * 64 + lane;
-      const bool h = i < len ? (i == 0 || (sk[i] >> 32) != (sk[i - 1] >> 32)) : i == len;
+      const bool h = i < len ? (i == 0 || (sk[i] >> rsh) != (sk[i - 1] >> rsh)) : i == len;
       const u64 m = __ballot(h);
       if (lane == 0) shw[j] = m;
     }
@@ -1433,7 +1439,7 @@ __global__ __launch_bounds__(GM_NT) void k_group_mid(Plan p, const u64* __restri
       }
     }
     if (__ballot(longrun) != 0) {
-      for (u32 pass = 0; pass < GM_DIGITS; ++pass) radix_pass(pass);
+      for (u32 pass = 0; pass < gd; ++pass) radix_pass(pass);
     } else {
 #pragma unroll
       for (int j = 0; j < GM_ITEMS; ++j) {
@@ -1588,6 +1594,8 @@ void launch_hist(const Plan& p, const K* src, hipStream_t s, u32 dlo) {
   tpw = tpw < 1 ? 1 : (tpw > HIST_TILES ? HIST_TILES : tpw);
   { const int pe_ = prof_begin(s); if (sizeof(K) == 8 && dlo == 5)
       hipLaunchKernelGGL((k_hist<K, 5>), dim3((p.max_tiles + tpw - 1) / tpw), dim3(SORT_NT), 0, s, p, src, tpw);
+    else if (sizeof(K) == 8 && dlo == 4)
+      hipLaunchKernelGGL((k_hist<K, 4>), dim3((p.max_tiles + tpw - 1) / tpw), dim3(SORT_NT), 0, s, p, src, tpw);
     else
       hipLaunchKernelGGL((k_hist<K, 0>), dim3((p.max_tiles + tpw - 1) / tpw), dim3(SORT_NT), 0, s, p, src, tpw); prof_end(pe_, p.only ? "hist_fallback" : "hist", s); }
   const u32 waves = p.NB * p.D;

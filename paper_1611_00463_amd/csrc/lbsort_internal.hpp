@@ -146,6 +146,11 @@ struct Plan {
   // x / m] (block_sample), so that the handler's samples need no strided
   // read of the sorted blocks.
   void* bsamp;
+  // The 64-bit fix-up path's group shift: the top-digit passes sort the
+  // blocks by key >> gshift (40: the three top digits; 32 for doubles, whose
+  // sign and exponent leave few distinct values in the top 24 bits: four),
+  // and the group fix-ups finish the groups of equal key >> gshift.
+  u32 gshift;
 };
 
 // The one-pass handler's sample problem (kernels_sampled.hip): the samples of
