@@ -843,7 +843,7 @@ def main():
         line["dups"] = {"workload": wd["desc"], "value": round(md["value"], 4), "unit": "GKeys/s",
                         "ms_per_step": round(md["ms"], 4), "imbalance": md["imbalance"],
                         "settings": md["settings"], "autotuned": md["autotuned"],
-                        "roofline": {k: rd[k] for k in ("kernel", "achieved", "frac", "avg_launch_ms")},
+                        "roofline": {k: rd[k] for k in ("kernel", "achieved", "frac", "avg_launch_ms", "traffic")},
                         "pipeline": {k: pd[k] for k in ("executed_bytes_per_key", "executed_frac", "model_frac")}}
         line["batched"] = run_batch(args, max(3, args.steps // 2), 1, tune=not args.no_tune)
     if cpu is not None:
