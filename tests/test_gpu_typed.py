@@ -134,6 +134,43 @@ def test_typed_local_sort(ws, dt):
             assert_same("vals", vo[x:y], (np.arange(x, y, dtype=np.uint32))[order])
 
 
+def _f64_top32_groups(rng, n_target, sizes, seed, low_bits=32):
+    """Doubles in groups of equal top 32 bits (sign, exponent, 20 fraction
+    bits) of the given sizes, in random order: the keys of a group differ in
+    their low `low_bits` bits, or (now and then) are all equal; half the
+    groups negative."""
+    parts, gid, total = [], 1, 0
+    while total < n_target:
+        g = int(sizes[rng.integers(0, len(sizes))])
+        low = datagen.uniform_keys(g, seed=seed + gid) >> np.uint64(64 - low_bits)
+        if rng.random() < 0.15:
+            low[:] = low[0]
+        top = (np.uint64(0x3FF + (gid % 7)) << np.uint64(52)) | (np.uint64((gid * 2654435761) % (1 << 20)) << np.uint64(32))
+        if gid % 2:
+            top |= np.uint64(1 << 63)
+        parts.append(top | low)
+        gid += 1
+        total += g
+    u = np.concatenate(parts)
+    return u[rng.permutation(len(u))].view(np.float64)
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_f64_groups_of_the_top_32_bits(ws, P):
+    """Doubles take four top-digit passes and are grouped by their top 32
+    bits: groups of every size class of the fix-up (ranked in place <= 64,
+    sorted by the mid-size kernel 65..512 over the four digits below, left
+    for the eight-pass sort above 512), and groups whose keys differ only in
+    their low 8 bits (long runs after the mid-size kernel's first pass)."""
+    rng = np.random.default_rng(90 + P)
+    for sizes, low_bits in (([1, 2, 63, 64, 65, 66, 200, 511, 512, 513, 900], 32),
+                            ([1, 64, 65, 100, 300, 512], 32),
+                            ([70, 200, 512], 8)):
+        keys = _f64_top32_groups(rng, 150_000 * P, sizes, 7000 * P + low_bits, low_bits)
+        print(f"[typed] f64 top-32 groups P={P} low_bits={low_bits} n={len(keys)}", flush=True)
+        run_index(keys, P, ws=ws)
+
+
 @pytest.mark.parametrize("dt", [np.uint64, np.uint32] + TYPES)
 def test_search_parity(ws, dt):
     n, P = 600_011, 16
